@@ -1,0 +1,260 @@
+"""Pins for the step-by-step tree oracle (``oracle/tree.py``).
+
+Each step is checked against something other than itself: hand values and the
+Z-order comparison for Morton codes, Python's stable sort, a bit-by-bit
+compressed trie for the radix tree, containment/union properties for the
+boxes, exact rational arithmetic for the quantization, and -- for the final
+node layout -- a plain CPU run of the paper's stackless traversal (Algorithm 1)
+over the emitted nodes, which must reproduce the brute-force neighbor lists.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import tree as T
+
+
+# ------------------------------------------------------------------- Morton codes
+
+def test_morton_hand_values():
+    box = np.full(3, 1023.0, np.float32)  # bin = floor(x), x in the lowest code bit
+    pts = np.array([[1.5, 0.5, 0.5], [0.5, 1.5, 0.5], [0.5, 0.5, 1.5], [0.5, 0.5, 0.5],
+                    [1022.5, 1022.5, 1022.5], [3.5, 0.5, 0.5]], np.float32)
+    codes = T.morton_keys(pts, box)
+    assert codes.tolist() == [1, 2, 4, 0, (1 << 30) - 1 - 7, 1 | 8]
+    typed = T.morton_keys(pts[:2], box, types=np.array([1, 3], np.int32))
+    assert typed.tolist() == [(1 << 30) | 1, (3 << 30) | 2]
+
+
+def _zorder_less(a, b):
+    # Z-order comparison without interleaving: the axis holding the most
+    # significant differing bit decides (z outranks y outranks x on equal bits).
+    best, axis = -1, 0
+    for d in range(3):
+        x = int(a[d]) ^ int(b[d])
+        if x and x.bit_length() - 1 >= best:
+            best, axis = x.bit_length() - 1, d
+    return best >= 0 and int(a[axis]) < int(b[axis])
+
+
+def test_morton_order_is_z_order():
+    rng = np.random.default_rng(0)
+    box = np.full(3, 1023.0, np.float32)
+    bins = rng.integers(0, 1023, size=(400, 3))
+    pts = (bins + 0.5).astype(np.float32)
+    codes = T.morton_keys(pts, box)
+    for _ in range(3000):
+        i, j = rng.integers(0, 400, 2)
+        assert (codes[i] < codes[j]) == _zorder_less(bins[i], bins[j])
+
+
+def test_morton_bins_cover_the_box():
+    pos, box = W.uniform(5000, [7.0, 9.0, 11.0], seed=1)
+    b = np.floor(pos.astype(np.float64) * (1023.0 / box.astype(np.float64)))
+    assert b.min() >= 0 and b.max() <= 1022
+
+
+# ------------------------------------------------------------------------ sort
+
+def test_sort_is_stable():
+    rng = np.random.default_rng(2)
+    keys = rng.integers(0, 20, size=500).astype(np.uint32)
+    sk, perm = T.sort_keys(keys)
+    ref = sorted(range(500), key=lambda i: (int(keys[i]), i))
+    assert perm.tolist() == ref
+    assert np.all(np.diff(sk.astype(np.int64)) >= 0)
+
+
+# ------------------------------------------------------------------ radix tree
+
+def _trie_nodes(sorted_keys, s, e):
+    """Binary radix tree as a compressed binary trie, built bit by bit from the top."""
+    a = [(int(sorted_keys[k]) << 32) | k for k in range(s, e)]
+    out = {}
+    stack = [(s, e - 1, 63)]
+    while stack:
+        f, l, bit = stack.pop()
+        if f == l:
+            continue
+        while True:  # skip bits on which the whole range agrees (unary trie nodes)
+            ones = [k for k in range(f, l + 1) if (a[k - s] >> bit) & 1]
+            if 0 < len(ones) < l - f + 1:
+                break
+            bit -= 1
+        gamma = ones[0] - 1
+        out[(f, l)] = gamma
+        stack.append((f, gamma, bit - 1))
+        stack.append((gamma + 1, l, bit - 1))
+    return out
+
+
+@pytest.mark.parametrize("n,ncode", [(2, 8), (3, 2), (17, 5), (64, 1), (200, 40), (300, 1 << 30)])
+def test_radix_tree_equals_compressed_trie(n, ncode):
+    rng = np.random.default_rng(n)
+    keys = np.sort(rng.integers(0, ncode, size=n).astype(np.uint32))
+    nodes = T.radix_tree(keys, 0, n)
+    assert nodes == _trie_nodes(keys, 0, n)
+    # N - 1 internal nodes, two children each, every leaf below exactly one parent
+    assert len(nodes) == n - 1
+    child_ranges = []
+    for (f, l), g in nodes.items():
+        assert f <= g < l
+        child_ranges += [(f, g), (g + 1, l)]
+    leaves = [r for r in child_ranges if r[0] == r[1]]
+    assert sorted(r[0] for r in leaves) == list(range(n))
+    assert (0, n - 1) in nodes
+
+
+def test_radix_tree_on_segment_offset():
+    keys = np.array([5, 1 << 30, (1 << 30) + 3, (1 << 30) + 3, (1 << 30) + 9], np.uint32)
+    nodes = T.radix_tree(keys, 1, 5)
+    assert nodes == _trie_nodes(keys, 1, 5)
+    assert (1, 4) in nodes and len(nodes) == 3
+
+
+# ---------------------------------------------------------------------- boxes
+
+def test_boxes_union_and_root():
+    cfg = W.lj_fluid(1500, seed=4)
+    b = T.build_all(cfg.pos, cfg.box)
+    (tree,), (boxes,) = b["trees"], b["boxes"]
+    p = b["sorted_pos"]
+
+    def box_of(f, l):
+        return (p[f], p[f]) if f == l else boxes[(f, l)]
+
+    for (f, l), g in tree.items():
+        lo, hi = boxes[(f, l)]
+        llo, lhi = box_of(f, g)
+        rlo, rhi = box_of(g + 1, l)
+        assert np.array_equal(lo, np.minimum(llo, rlo)) and np.array_equal(hi, np.maximum(lhi, rhi))
+    lo, hi = boxes[(0, cfg.n - 1)]
+    assert np.array_equal(lo, cfg.pos.min(axis=0)) and np.array_equal(hi, cfg.pos.max(axis=0))
+
+
+# ---------------------------------------------------------------- quantization
+
+@pytest.mark.parametrize("qbits", [10, 16])
+def test_quantized_bounds_are_outward_and_within_one_bin(qbits):
+    cfg = W.lj_fluid(800, seed=6)
+    b = T.build_all(cfg.pos, cfg.box, qbits=qbits)
+    (boxes,) = b["boxes"]
+    rlo, rhi = boxes[(0, cfg.n - 1)]
+    h = T.grid_spacing(rlo, rhi, cfg.box, qbits)
+    assert h * ((1 << qbits) - 1) >= float(np.max(rhi.astype(np.float64) - rlo.astype(np.float64)))
+    H = Fraction(h)
+    tol = Fraction(1, 10 ** 9)  # fp64 evaluation error, far below the traversal's 2-bin pad
+    for (f, l), (lo, hi) in list(boxes.items())[:300]:
+        qlo, qhi = T.quantize_box(lo, hi, rlo, h, qbits)
+        for d in range(3):
+            assert 0 <= qlo[d] <= qhi[d] <= (1 << qbits) - 1
+            glo = (Fraction(float(lo[d])) - Fraction(float(rlo[d]))) / H
+            ghi = (Fraction(float(hi[d])) - Fraction(float(rlo[d]))) / H
+            assert qlo[d] <= glo + tol and qhi[d] >= ghi - tol      # outward
+            assert qlo[d] > glo - 1 and qhi[d] < ghi + 1              # at most one bin loose
+
+
+def test_grid_spacing_floor_for_coincident_points():
+    lo = hi = np.array([1.0, 2.0, 3.0], np.float32)
+    h = T.grid_spacing(lo, hi, np.full(3, 10.0, np.float32), 16)
+    assert h == 10.0 * 2.0 ** -24 / 65535
+
+
+# --------------------------------------------------- layout: Algorithm 1 on the CPU
+
+def _alg1_rows(slots, meta, box, rlist2, qtypes, qpos, orig_of_query):
+    """The paper's stackless traversal over the emitted layout, in plain Python.
+
+    Internal slot: decode the quantized box (root lo + q * h) and test it
+    against the search sphere (nearest point, eq. 2) with a tiny pad; on
+    overlap go to the next slot, else follow the rope.  Particle slot: exact
+    fp64 minimum-image distance as the list definition; then the next slot.
+    """
+    L = np.asarray(box, np.float64)
+    rows = []
+    for qi in range(qpos.shape[0]):
+        x = qpos[qi].astype(np.float64)
+        ta = qtypes[qi]
+        found = []
+        for tb, m in enumerate(meta):
+            r2 = rlist2[ta, tb]
+            if m["count"] == 0 or r2 < 0:
+                continue
+            R = np.sqrt(r2)
+            rlo = m["lo"].astype(np.float64)
+            rhi = m["hi"].astype(np.float64)
+            for img in range(27):
+                shift = np.array([img % 3 - 1, (img // 3) % 3 - 1, img // 9 - 1], np.float64)
+                c = x + shift * L
+                y = np.minimum(np.maximum(c, rlo), rhi)
+                if np.sum((y - c) ** 2) > r2 * (1 + 1e-12):
+                    continue
+                n = m["root"]
+                while n < m["end"]:
+                    w = slots[n]
+                    if int(w[3]) >= 1 << 31:  # particle (negative index encoding)
+                        pj = w[:3].view(np.float32).astype(np.float64)
+                        dx = (pj - x) - shift * L
+                        d2 = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2]
+                        j = int(np.int64(~np.int64(np.int32(np.uint32(w[3])))))
+                        if d2 <= r2 and j != orig_of_query[qi]:
+                            found.append(j)
+                        n += 1
+                    else:
+                        qlo = np.array([int(w[d]) & 0xFFFF for d in range(3)], np.float64)
+                        qhi = np.array([int(w[d]) >> 16 for d in range(3)], np.float64)
+                        lo = rlo + qlo * m["h"]
+                        hi = rlo + qhi * m["h"]
+                        y = np.minimum(np.maximum(c, lo), hi)
+                        if np.sqrt(np.sum((y - c) ** 2)) <= R * (1 + 1e-9) + 1e-9:
+                            n += 1
+                        else:
+                            n = int(w[3])
+        rows.append(sorted(found))
+    return rows
+
+
+@pytest.mark.parametrize("leaf_size,qbits", [(1, 16), (1, 10), (3, 16), (8, 12)])
+def test_layout_traversal_reproduces_brute_force(leaf_size, qbits):
+    cfg = W.lj_fluid(350, seed=8, rho=0.6, rc=2.0, skin=0.3)
+    b = T.build_all(cfg.pos, cfg.box, leaf_size=leaf_size, qbits=qbits)
+    r2 = oracle.rlist2_table(cfg.rcut, cfg.skin)
+    perm = b["perm"].astype(np.int64)
+    rows = _alg1_rows(b["slots"], b["meta"], cfg.box, r2, np.zeros(cfg.n, np.int64),
+                      b["sorted_pos"], perm)
+    rp, cols = oracle.neighbor_lists(cfg.pos, cfg.box, cfg.rcut, cfg.skin, method="brute")
+    for k in range(cfg.n):
+        i = perm[k]
+        assert rows[k] == cols[rp[i]:rp[i + 1]].tolist()
+    # slot count = particles + kept internal nodes (ranges larger than a leaf)
+    kept = sum(1 for (f, l) in b["trees"][0] if l - f + 1 > leaf_size)
+    assert b["slots"].shape[0] == cfg.n + kept
+
+
+def test_layout_two_types_and_empty_type():
+    pos, box = W.uniform(300, [9.0, 9.0, 9.0], seed=13)
+    types = (np.arange(300) % 4 == 0).astype(np.int32) * 2  # types 0 and 2, type 1 empty
+    rcut = np.array([[1.2, 0.0, 1.6], [0.0, 1.0, 0.0], [1.6, 0.0, 2.0]], np.float32)
+    b = T.build_all(pos, box, types=types, ntypes=3, leaf_size=2)
+    assert b["meta"][1]["count"] == 0
+    r2 = oracle.rlist2_table(rcut, 0.25)
+    perm = b["perm"].astype(np.int64)
+    rows = _alg1_rows(b["slots"], b["meta"], box, r2, types[perm], b["sorted_pos"], perm)
+    rp, cols = oracle.neighbor_lists(pos, box, rcut, 0.25, types=types, method="brute")
+    for k in range(300):
+        i = perm[k]
+        assert sorted(rows[k]) == cols[rp[i]:rp[i + 1]].tolist()
+
+
+def test_layout_ropes_point_forward_and_end_at_tree_end():
+    cfg = W.lj_fluid(500, seed=9)
+    b = T.build_all(cfg.pos, cfg.box, leaf_size=2)
+    s = b["slots"]
+    (m,) = b["meta"]
+    internal = s[:, 3] < (1 << 31)
+    idx = np.nonzero(internal)[0]
+    assert np.all(s[idx, 3] > idx) and np.all(s[idx, 3] <= m["end"])
+    assert s[m["root"], 3] == m["end"]  # the root's rope leaves the tree

@@ -1,0 +1,326 @@
+"""Seeded synthetic particle configurations for the neighbor-search workloads.
+
+These generators stand in for the molecular-dynamics snapshots the paper
+benchmarks (Section 4: Lennard-Jones fluid at fixed density in a cubic periodic
+box; the size-asymmetric colloid/solvent mixtures of the authors' earlier BVH
+work; liquid/vapor inhomogeneity as in the spinodal benchmark).  No snapshot
+data is available, so every configuration is drawn from a seeded NumPy
+generator with the same box shape, density and particle count.
+
+This module holds inputs only: no neighbor-search arithmetic lives here, and it
+imports neither the HIP library nor the oracle.  Every generator returns
+positions as C-contiguous float32 ``[N, 3]`` arrays inside the half-open box
+``[0, L_d)`` on each axis, together with the box as float32 ``[3]``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Config",
+    "wrap_f32",
+    "lj_lattice",
+    "uniform",
+    "sc_lattice",
+    "lj_fluid",
+    "colloid_solvent",
+    "ensemble",
+    "slab",
+    "SEEDS",
+]
+
+# Seeds fixed per workload so every consumer sees the same particles.
+SEEDS = {
+    "lj4000": 19010881,
+    "lj1m": 19010882,
+    "lj8m": 19010883,
+    "colloid": 19010884,
+    "ensemble": 19010885,
+    "served": 19010886,
+}
+
+
+@dataclass
+class Config:
+    """One particle configuration plus the cutoff table it is searched with."""
+
+    pos: np.ndarray  # float32 [N, 3]
+    box: np.ndarray  # float32 [3]
+    rcut: np.ndarray  # float32 [ntypes, ntypes]
+    skin: float
+    types: np.ndarray | None = None  # int32 [N] or None for one type
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def ntypes(self) -> int:
+        return int(self.rcut.shape[0])
+
+
+def wrap_f32(x64: np.ndarray, box32: np.ndarray) -> np.ndarray:
+    """Wrap fp64 coordinates into [0, L) and round them to fp32.
+
+    The wrap is done in fp64 against the exact fp32 box edge; a value that
+    rounds up to L after conversion is mapped onto 0 so the result lies in the
+    half-open box.
+    """
+    L = box32.astype(np.float64)
+    w = np.mod(x64, L)
+    w = np.where(w < 0.0, w + L, w)
+    out = w.astype(np.float32)
+    out = np.where(out >= box32, np.float32(0.0), out)
+    out = np.where(out < 0, np.float32(0.0), out)
+    return np.ascontiguousarray(out, dtype=np.float32)
+
+
+def _lattice_n(n_particles: int) -> int:
+    n = int(round(n_particles ** (1.0 / 3.0)))
+    while n ** 3 < n_particles:
+        n += 1
+    while n > 1 and (n - 1) ** 3 >= n_particles:
+        n -= 1
+    return n
+
+
+def lj_lattice(n_particles: int, rho: float, seed, jitter: float = 0.3,
+               box: np.ndarray | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """Jittered simple-cubic lattice at number density ``rho`` in a cubic box.
+
+    L = (N / rho)^(1/3); the lattice has n = ceil(N^(1/3)) sites per axis with
+    spacing a = L / n, N sites are picked by a seeded permutation (so particle
+    order is random, as in an unsorted snapshot) and each coordinate gets a
+    uniform displacement in [-jitter, +jitter].
+    """
+    rng = np.random.default_rng(seed)
+    if box is None:
+        L = (n_particles / rho) ** (1.0 / 3.0)
+        box32 = np.full(3, L, dtype=np.float32)
+    else:
+        box32 = np.asarray(box, dtype=np.float32)
+    n = _lattice_n(n_particles)
+    a = box32.astype(np.float64) / n
+    sites = rng.permutation(n ** 3)[:n_particles]
+    iz, rem = np.divmod(sites, n * n)
+    iy, ix = np.divmod(rem, n)
+    m = np.stack([ix, iy, iz], axis=1).astype(np.float64)
+    x = (m + 0.5) * a + rng.uniform(-jitter, jitter, size=(n_particles, 3))
+    return wrap_f32(x, box32), box32
+
+
+def uniform(n_particles: int, box, seed) -> tuple[np.ndarray, np.ndarray]:
+    """Independent uniform (ideal-gas) positions in an orthorhombic box."""
+    rng = np.random.default_rng(seed)
+    box32 = np.asarray(box, dtype=np.float32).reshape(3)
+    x = rng.uniform(0.0, 1.0, size=(n_particles, 3)) * box32.astype(np.float64)
+    return wrap_f32(x, box32), box32
+
+
+def sc_lattice(n: int, a: float = 1.0) -> tuple[np.ndarray, np.ndarray]:
+    """Perfect simple-cubic lattice with n sites per axis, spacing a, at m*a."""
+    g = np.arange(n, dtype=np.float64) * a
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    box32 = np.full(3, n * a, dtype=np.float32)
+    return wrap_f32(pos, box32), box32
+
+
+def lj_fluid(n_particles: int, seed=None, rho: float = 0.85, rc: float = 3.0,
+             skin: float = 0.4) -> Config:
+    """Single-type Lennard-Jones-fluid stand-in (jittered lattice), rc and skin in sigma."""
+    if seed is None:
+        seed = {4000: SEEDS["lj4000"], 1_000_000: SEEDS["lj1m"],
+                8_000_000: SEEDS["lj8m"]}.get(n_particles, SEEDS["lj4000"])
+    pos, box = lj_lattice(n_particles, rho, seed)
+    return Config(pos=pos, box=box, rcut=np.array([[rc]], dtype=np.float32), skin=skin,
+                  name=f"lj_fluid_N{n_particles}_rho{rho}",
+                  meta={"rho": rho, "seed": seed})
+
+
+def _rsa_insert(rng, box64, n_target, diam_new, existing, cross_min, self_min,
+                batch=65536, max_rounds=100000):
+    """Random sequential addition with a cell grid.
+
+    ``existing`` is a list of (positions [M,3], min distance to a new particle).
+    New particles must be at least ``self_min`` apart from each other.  Trial
+    points are drawn in batches; conflicts within a batch are resolved in draw
+    order so the result is the same as one-at-a-time insertion order.
+    """
+    del diam_new
+    placed = np.empty((0, 3), dtype=np.float64)
+    cell = max([self_min] + [d for _, d in existing])
+    ncell = np.maximum((box64 // cell).astype(np.int64), 1)
+    width = box64 / ncell
+
+    def build_grid(pts):
+        c = np.minimum((pts // width).astype(np.int64), ncell - 1)
+        lin = (c[:, 0] * ncell[1] + c[:, 1]) * ncell[2] + c[:, 2]
+        order = np.argsort(lin, kind="stable")
+        starts = np.searchsorted(lin[order], np.arange(ncell.prod() + 1))
+        return order, starts
+
+    grids = [(p, d, *build_grid(p)) for p, d in existing]
+    offsets = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+
+    def conflicts(trial, pts, dmin, order, starts):
+        if pts.shape[0] == 0:
+            return np.zeros(trial.shape[0], dtype=bool)
+        c = np.minimum((trial // width).astype(np.int64), ncell - 1)
+        bad = np.zeros(trial.shape[0], dtype=bool)
+        for off in offsets:
+            cc = np.mod(c + off, ncell)
+            lin = (cc[:, 0] * ncell[1] + cc[:, 1]) * ncell[2] + cc[:, 2]
+            lo = starts[lin]
+            hi = starts[lin + 1]
+            cnt = hi - lo
+            maxc = int(cnt.max()) if cnt.size else 0
+            for s in range(maxc):
+                has = cnt > s
+                if not has.any():
+                    break
+                idx = order[lo[has] + s]
+                d = pts[idx] - trial[has]
+                d -= box64 * np.round(d / box64)
+                r2 = np.einsum("ij,ij->i", d, d)
+                bad[np.nonzero(has)[0][r2 < dmin * dmin]] = True
+        return bad
+
+    rounds = 0
+    while placed.shape[0] < n_target:
+        rounds += 1
+        if rounds > max_rounds:
+            raise RuntimeError("random sequential addition did not converge")
+        trial = rng.uniform(0.0, 1.0, size=(batch, 3)) * box64
+        ok = np.ones(batch, dtype=bool)
+        for pts, dmin, order, starts in grids:
+            ok &= ~conflicts(trial, pts, dmin, order, starts)
+        if placed.shape[0]:
+            po, ps = build_grid(placed)
+            ok &= ~conflicts(trial, placed, self_min, po, ps)
+        trial = trial[ok]
+        if trial.shape[0] == 0:
+            continue
+        # resolve conflicts inside the batch in draw order (greedy, sequential semantics)
+        keep = []
+        tgrid = {}
+        for t_i, p in enumerate(trial):
+            cidx = tuple(np.minimum((p // width).astype(np.int64), ncell - 1))
+            clash = False
+            for off in offsets:
+                key = tuple(np.mod(np.array(cidx) + off, ncell))
+                for q in tgrid.get(key, ()):
+                    d = trial[q] - p
+                    d -= box64 * np.round(d / box64)
+                    if d @ d < self_min * self_min:
+                        clash = True
+                        break
+                if clash:
+                    break
+            if not clash:
+                keep.append(t_i)
+                tgrid.setdefault(cidx, []).append(t_i)
+                if placed.shape[0] + len(keep) >= n_target:
+                    break
+        placed = np.concatenate([placed, trial[keep]], axis=0)
+    return placed[:n_target]
+
+
+def colloid_solvent(n_total: int = 1_000_000, seed=SEEDS["colloid"], frac_colloid: float = 0.02,
+                    d_colloid: float = 5.0, rho_solvent_accessible: float = 0.5,
+                    skin: float = 0.4) -> Config:
+    """Binary colloid/solvent mixture placed by random sequential addition.
+
+    Type 0 = solvent (diameter 1), type 1 = colloid (diameter ``d_colloid``).
+    The solvent density is read as the number density in the volume that
+    solvent centers can reach (box minus the colloid exclusion shells of radius
+    (1 + d_colloid) / 2): any reading against the total box volume would need a
+    colloid volume fraction above the random-sequential-addition jamming limit.
+    Cutoffs are rc_ij = (sigma_i + sigma_j) / 2 and the list radius adds ``skin``.
+    """
+    rng = np.random.default_rng(seed)
+    n_c = int(round(frac_colloid * n_total))
+    n_s = n_total - n_c
+    r_excl = 0.5 * (1.0 + d_colloid)
+    v_excl = n_c * (4.0 / 3.0) * math.pi * r_excl ** 3
+    volume = n_s / rho_solvent_accessible + v_excl
+    L = volume ** (1.0 / 3.0)
+    box32 = np.full(3, L, dtype=np.float32)
+    box64 = box32.astype(np.float64)
+    col = _rsa_insert(rng, box64, n_c, d_colloid, [], 0.0, d_colloid)
+    sol = _rsa_insert(rng, box64, n_s, 1.0, [(col, r_excl)], r_excl, 1.0)
+    pos64 = np.concatenate([sol, col], axis=0)
+    types = np.concatenate([np.zeros(n_s, np.int32), np.ones(n_c, np.int32)])
+    perm = rng.permutation(n_total)
+    pos = wrap_f32(pos64[perm], box32)
+    types = types[perm]
+    sig = np.array([1.0, d_colloid])
+    rcut = (0.5 * (sig[:, None] + sig[None, :])).astype(np.float32)
+    return Config(pos=pos, box=box32, rcut=rcut, skin=skin, types=np.ascontiguousarray(types),
+                  name=f"colloid_solvent_N{n_total}",
+                  meta={"seed": seed, "n_colloid": n_c, "n_solvent": n_s, "L": float(L),
+                        "colloid_volume_fraction": n_c * (math.pi / 6) * d_colloid ** 3 / volume})
+
+
+def ensemble(n_systems: int = 256, seed=SEEDS["ensemble"], n_min: int = 2000, n_max: int = 200_000,
+             rho_lo: float = 0.3, rho_hi: float = 0.9, rc_lo: float = 2.5, rc_hi: float = 3.0,
+             skin: float = 0.4, scale: float = 1.0) -> list[Config]:
+    """Independent Lennard-Jones replicas with log-uniform N and uniform density and cutoff.
+
+    ``scale`` shrinks every N (for CPU-sized tests) without changing the draws.
+    """
+    children = np.random.SeedSequence(seed).spawn(n_systems)
+    out = []
+    for k, ss in enumerate(children):
+        rng = np.random.default_rng(ss)
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        rho = float(rng.uniform(rho_lo, rho_hi))
+        rc = float(rng.uniform(rc_lo, rc_hi))
+        n = max(2, int(round(n * scale)))
+        pos_seed = int(rng.integers(0, 2 ** 63 - 1))
+        pos, box = lj_lattice(n, rho, pos_seed)
+        out.append(Config(pos=pos, box=box, rcut=np.array([[rc]], dtype=np.float32), skin=skin,
+                          name=f"replica{k}_N{n}", meta={"rho": rho, "rc": rc, "index": k}))
+    return out
+
+
+def slab(n_target_liquid_thickness: float = 80.0, seed=SEEDS["served"], box=(60.0, 60.0, 240.0),
+         rho_liquid: float = 0.8, rho_vapor: float = 0.02, min_vapor_gap: float = 0.8,
+         rc: float = 3.0, skin: float = 0.4) -> Config:
+    """Liquid slab (jittered lattice at ``rho_liquid``) in a dilute uniform vapor.
+
+    The liquid fills |z - Lz/2| < t/2; vapor points are uniform elsewhere and
+    are rejected closer than ``min_vapor_gap`` to any liquid particle.
+    """
+    rng = np.random.default_rng(seed)
+    box32 = np.asarray(box, dtype=np.float32)
+    box64 = box32.astype(np.float64)
+    t = float(n_target_liquid_thickness)
+    a = rho_liquid ** (-1.0 / 3.0)
+    nx, ny = int(round(box64[0] / a)), int(round(box64[1] / a))
+    nz = max(1, int(round(t / a)))
+    ax, ay, az = box64[0] / nx, box64[1] / ny, t / nz
+    g = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"),
+                 axis=-1).reshape(-1, 3).astype(np.float64)
+    liq = (g + 0.5) * np.array([ax, ay, az])
+    liq[:, 2] += box64[2] / 2 - t / 2
+    liq += rng.uniform(-0.3, 0.3, size=liq.shape) * np.array([ax, ay, az]) / a
+    v_vap = box64[0] * box64[1] * (box64[2] - t)
+    n_vap = int(round(rho_vapor * v_vap))
+    vap = np.empty((0, 3))
+    while vap.shape[0] < n_vap:
+        trial = rng.uniform(0.0, 1.0, size=(2 * n_vap + 16, 3)) * box64
+        dz = np.abs(trial[:, 2] - box64[2] / 2)
+        trial = trial[dz >= t / 2 + min_vapor_gap]
+        vap = np.concatenate([vap, trial[: n_vap - vap.shape[0]]], axis=0)
+    pos64 = np.concatenate([liq, vap], axis=0)
+    pos64 = pos64[rng.permutation(pos64.shape[0])]
+    pos = wrap_f32(pos64, box32)
+    return Config(pos=pos, box=box32, rcut=np.array([[rc]], dtype=np.float32), skin=skin,
+                  name=f"slab_t{t:g}_N{pos.shape[0]}",
+                  meta={"seed": seed, "n_liquid": liq.shape[0], "n_vapor": n_vap})
