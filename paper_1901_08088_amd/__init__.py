@@ -1,0 +1,14 @@
+"""Quantized-BVH neighbor lists for AMD Instinct MI355X (gfx950).
+
+The neighbor search runs in hand-written HIP kernels behind the C interface
+declared in ``include/qbvh.h`` (``libqbvh.so``, built in-tree by
+``build_ext.py``).  ``capi`` is a thin ctypes binding with the same names.
+The library is loaded on first use, not at import.
+"""
+from .capi import (EXPORT, QbvhError, QbvhOpts, Tree, lib, nlist_build, nlist_build_many,  # noqa: F401
+                   qbvh_build, qbvh_export, qbvh_free, qbvh_info, qbvh_strerror,
+                   qbvh_workspace_bytes)
+
+__all__ = ["EXPORT", "QbvhError", "QbvhOpts", "Tree", "lib", "nlist_build", "nlist_build_many",
+           "qbvh_build", "qbvh_export", "qbvh_free", "qbvh_info", "qbvh_strerror",
+           "qbvh_workspace_bytes"]

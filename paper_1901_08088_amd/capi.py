@@ -1,0 +1,257 @@
+"""ctypes binding of ``libqbvh.so`` (the C interface declared in include/qbvh.h).
+
+Argument marshalling only: torch tensors become device pointers, the current
+torch stream becomes the hipStream_t, and negative return codes become
+``QbvhError``.  Every step of the neighbor search runs in the library's HIP
+kernels; there is no fallback.  If the library is missing this module raises
+when it is first used.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqbvh.so")
+
+MAX_TYPES = 4
+OK, EINVAL, EGEOM, ENOMEM, EHIP, EAGAIN, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+EXPORT = dict(keys=1, perm=2, sorted=3, left=4, right=5, range_f=6, range_l=7, parent=8,
+              leaf_parent=9, box_lo=10, box_hi=11, slots=12)
+
+C_API = ("qbvh_build", "nlist_build", "nlist_build_many", "qbvh_free", "qbvh_strerror",
+         "qbvh_last_hip_error", "qbvh_workspace_bytes", "qbvh_info", "qbvh_export")
+
+
+class QbvhError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = qbvh_strerror(code)
+        if code == EHIP:
+            msg += f" (hipError {lib().qbvh_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{code}]")
+
+
+class QbvhOpts(ctypes.Structure):
+    _fields_ = [("leaf_size", ctypes.c_int32), ("qbits", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("validate", ctypes.c_int32)]
+
+
+class QbvhBatchOpts(ctypes.Structure):
+    _fields_ = [("leaf_size", ctypes.c_int32), ("qbits", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class QbvhSystem(ctypes.Structure):
+    _fields_ = [("d_pos", ctypes.c_void_p), ("d_type", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("ntypes", ctypes.c_int32), ("box", ctypes.c_float * 3), ("rcut", ctypes.c_void_p),
+                ("skin", ctypes.c_float), ("max_nbr", ctypes.c_int32), ("d_nbr", ctypes.c_void_p),
+                ("d_count", ctypes.c_void_p), ("d_overflow", ctypes.c_void_p)]
+
+
+class QbvhInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("ntypes", ctypes.c_int32), ("nslots", ctypes.c_int32),
+                ("leaf_size", ctypes.c_int32), ("qbits", ctypes.c_int32),
+                ("tree_start", ctypes.c_int32 * MAX_TYPES), ("tree_count", ctypes.c_int32 * MAX_TYPES),
+                ("tree_root", ctypes.c_int32 * MAX_TYPES), ("tree_end", ctypes.c_int32 * MAX_TYPES),
+                ("root_lo", (ctypes.c_float * 3) * MAX_TYPES), ("root_hi", (ctypes.c_float * 3) * MAX_TYPES),
+                ("h", ctypes.c_double * MAX_TYPES)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load libqbvh.so once; raise if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                                   "`python -m paper_1901_08088_amd.build_ext` (hipcc, gfx950)")
+            L = ctypes.CDLL(LIB_PATH)
+            P, I32 = ctypes.c_void_p, ctypes.c_int32
+            L.qbvh_build.argtypes = [ctypes.POINTER(P), P, P, I32, I32, ctypes.POINTER(ctypes.c_float),
+                                     ctypes.POINTER(QbvhOpts), P]
+            L.qbvh_build.restype = ctypes.c_int
+            L.nlist_build.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_float, I32, P, P, P, P]
+            L.nlist_build.restype = ctypes.c_int
+            L.nlist_build_many.argtypes = [I32, ctypes.POINTER(QbvhSystem), ctypes.POINTER(QbvhBatchOpts), P]
+            L.nlist_build_many.restype = ctypes.c_int
+            L.qbvh_free.argtypes = [P]
+            L.qbvh_free.restype = None
+            L.qbvh_strerror.argtypes = [ctypes.c_int]
+            L.qbvh_strerror.restype = ctypes.c_char_p
+            L.qbvh_last_hip_error.argtypes = []
+            L.qbvh_last_hip_error.restype = ctypes.c_int
+            L.qbvh_workspace_bytes.argtypes = [I32, I32, ctypes.POINTER(QbvhOpts)]
+            L.qbvh_workspace_bytes.restype = ctypes.c_size_t
+            L.qbvh_info.argtypes = [P, ctypes.POINTER(QbvhInfo)]
+            L.qbvh_info.restype = ctypes.c_int
+            L.qbvh_export.argtypes = [P, I32, P, ctypes.c_size_t, P]
+            L.qbvh_export.restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, name, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opts(opts) -> QbvhOpts | None:
+    if opts is None:
+        return None
+    if isinstance(opts, QbvhOpts):
+        return opts
+    o = QbvhOpts()
+    for k, v in dict(opts).items():
+        setattr(o, k, int(v))
+    return o
+
+
+def _check(code: int, where: str):
+    if code != OK:
+        raise QbvhError(code, where)
+
+
+class Tree:
+    """Owns a ``qbvh_t*``; freed by ``qbvh_free`` or when garbage collected."""
+
+    def __init__(self):
+        self.ptr = ctypes.c_void_p(None)
+        self.ntypes = 1
+
+    def __del__(self):
+        try:
+            qbvh_free(self)
+        except Exception:
+            pass
+
+
+def qbvh_build(pos, types=None, box=None, ntypes: int = 1, opts=None, tree: Tree | None = None,
+               stream=None) -> Tree:
+    """Build (or rebuild in place) the quantized BVH of ``pos`` (float32 [n, 3] on the GPU)."""
+    import torch
+    t = tree if tree is not None else Tree()
+    n = int(pos.shape[0]) if pos is not None else 0
+    if pos is not None and (pos.dim() != 2 or pos.shape[1] != 3):
+        raise ValueError("pos must have shape [n, 3]")
+    pp = _dev_ptr(pos, torch.float32, "pos")
+    tp = _dev_ptr(types, torch.int32, "types", allow_none=True)
+    b = (ctypes.c_float * 3)(*[float(x) for x in np.asarray(box, dtype=np.float32).reshape(3)])
+    o = _opts(opts)
+    rc = lib().qbvh_build(ctypes.byref(t.ptr), pp, tp, n, int(ntypes), b,
+                          ctypes.byref(o) if o is not None else None, _stream(stream))
+    _check(rc, "qbvh_build")
+    t.ntypes = int(ntypes)
+    return t
+
+
+def _rcut_array(rcut, ntypes):
+    rc = np.ascontiguousarray(np.asarray(rcut, dtype=np.float32).reshape(ntypes, ntypes))
+    return rc, rc.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def nlist_build(tree: Tree, rcut, skin: float, max_nbr: int, nbr, count, overflow, stream=None) -> None:
+    """Exact neighbor list of the tree's particles into caller-owned device tensors."""
+    import torch
+    rc, rp = _rcut_array(rcut, tree.ntypes)
+    rc_ = lib().nlist_build(tree.ptr, rp, float(skin), int(max_nbr),
+                            _dev_ptr(nbr, torch.int32, "nbr", allow_none=True),
+                            _dev_ptr(count, torch.int32, "count"), _dev_ptr(overflow, torch.int32, "overflow"),
+                            _stream(stream))
+    del rc
+    _check(rc_, "nlist_build")
+
+
+def nlist_build_many(systems, opts=None, stream=None) -> None:
+    """Batched build + traversal.  ``systems`` is a list of dicts with the keys of qbvh_system_t
+    (pos, types, box, rcut, skin, max_nbr, nbr, count, overflow; ntypes optional)."""
+    import torch
+    arr = (QbvhSystem * max(len(systems), 1))()
+    keep = []
+    for i, s in enumerate(systems):
+        ntypes = int(s.get("ntypes", 1))
+        rc, rp = _rcut_array(s["rcut"], ntypes)
+        keep.append(rc)
+        y = arr[i]
+        y.d_pos = _dev_ptr(s["pos"], torch.float32, "pos")
+        y.d_type = _dev_ptr(s.get("types"), torch.int32, "types", allow_none=True)
+        y.n = int(s["pos"].shape[0])
+        y.ntypes = ntypes
+        for d, v in enumerate(np.asarray(s["box"], dtype=np.float32).reshape(3)):
+            y.box[d] = float(v)
+        y.rcut = ctypes.cast(rp, ctypes.c_void_p)
+        y.skin = float(s["skin"])
+        y.max_nbr = int(s["max_nbr"])
+        y.d_nbr = _dev_ptr(s.get("nbr"), torch.int32, "nbr", allow_none=True)
+        y.d_count = _dev_ptr(s["count"], torch.int32, "count")
+        y.d_overflow = _dev_ptr(s["overflow"], torch.int32, "overflow")
+    o = None
+    if opts is not None:
+        o = QbvhBatchOpts(**{k: int(v) for k, v in dict(opts).items()})
+    rc_ = lib().nlist_build_many(len(systems), arr, ctypes.byref(o) if o is not None else None,
+                                 _stream(stream))
+    del keep
+    _check(rc_, "nlist_build_many")
+
+
+def qbvh_free(tree: Tree) -> None:
+    if tree is not None and tree.ptr:
+        lib().qbvh_free(tree.ptr)
+        tree.ptr = ctypes.c_void_p(None)
+
+
+def qbvh_strerror(code: int) -> str:
+    return lib().qbvh_strerror(int(code)).decode()
+
+
+def qbvh_workspace_bytes(n: int, ntypes: int = 1, opts=None) -> int:
+    o = _opts(opts)
+    return int(lib().qbvh_workspace_bytes(int(n), int(ntypes), ctypes.byref(o) if o is not None else None))
+
+
+def qbvh_info(tree: Tree) -> dict:
+    """Host summary of a built tree (synchronizes the tree's last stream)."""
+    info = QbvhInfo()
+    _check(lib().qbvh_info(tree.ptr, ctypes.byref(info)), "qbvh_info")
+    nt = info.ntypes
+    return dict(n=info.n, ntypes=nt, nslots=info.nslots, leaf_size=info.leaf_size, qbits=info.qbits,
+                tree_start=list(info.tree_start)[:nt], tree_count=list(info.tree_count)[:nt],
+                tree_root=list(info.tree_root)[:nt], tree_end=list(info.tree_end)[:nt],
+                root_lo=[list(info.root_lo[t]) for t in range(nt)],
+                root_hi=[list(info.root_hi[t]) for t in range(nt)], h=list(info.h)[:nt])
+
+
+def qbvh_export(tree: Tree, what, dst, stream=None) -> None:
+    """Copy an intermediate array of the last build into the device tensor ``dst``."""
+    code = EXPORT[what] if isinstance(what, str) else int(what)
+    if not dst.is_cuda or not dst.is_contiguous():
+        raise ValueError("dst must be a contiguous CUDA tensor")
+    nbytes = dst.numel() * dst.element_size()
+    _check(lib().qbvh_export(tree.ptr, code, ctypes.c_void_p(dst.data_ptr()), nbytes, _stream(stream)),
+           "qbvh_export")

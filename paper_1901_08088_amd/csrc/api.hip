@@ -1,0 +1,285 @@
+// C interface of the qbvh library: argument checks, workspace ownership and
+// launch sequencing.  All device work is in build.hip, sort.hip and
+// traverse.hip; nothing here computes on the host beyond the per-call
+// constants (list radii, box scale factors).
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "qbvh_internal.h"
+
+using qbi::TreeMeta;
+using qbi::Workspace;
+
+struct qbvh {
+    Workspace ws;
+    int32_t n = 0;
+    int32_t ntypes = 1;
+    float box[3] = {0.f, 0.f, 0.f};
+    qbvh_opts_t opts{};
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+int hip_fail(hipError_t e) {
+    g_last_hip_error = (int)e;
+    (void)hipGetLastError();  // clear the sticky launch error
+    return e == hipErrorOutOfMemory ? QBVH_ENOMEM : QBVH_EHIP;
+}
+
+int resolve_opts(const qbvh_opts_t *in, qbvh_opts_t *out) {
+    qbvh_opts_t o{};
+    if (in) o = *in;
+    if (o.leaf_size == 0) o.leaf_size = 1;
+    if (o.qbits == 0) o.qbits = 16;
+    if (o.block_size == 0) o.block_size = 256;
+    if (o.leaf_size < 1 || o.leaf_size > 32) return QBVH_EINVAL;
+    if (o.qbits < 8 || o.qbits > 16) return QBVH_EINVAL;
+    // the traversal kernel is compiled for at most 256 work-items per group
+    if (o.block_size < 64 || o.block_size > 256 || (o.block_size % 64) != 0) return QBVH_EINVAL;
+    if (o.validate != 0 && o.validate != 1) return QBVH_EINVAL;
+    *out = o;
+    return QBVH_OK;
+}
+
+bool box_ok(const float box[3]) {
+    if (!box) return false;
+    for (int d = 0; d < 3; ++d)
+        if (!(isfinite(box[d]) && box[d] > 0.0f)) return false;
+    return true;
+}
+
+constexpr int32_t kMaxParticles = (1 << 30) - 1;
+
+// (rc + skin)^2 in fp64 from the fp32 inputs; -1 marks a pair never listed.
+int list_radii(const float *rcut, float skin, int32_t ntypes, const float box[3],
+               double rlist2[QBVH_MAX_TYPES * QBVH_MAX_TYPES]) {
+    if (!rcut || !(isfinite(skin) && skin >= 0.0f)) return QBVH_EINVAL;
+    double rmax = 0.0;
+    for (int a = 0; a < QBVH_MAX_TYPES * QBVH_MAX_TYPES; ++a) rlist2[a] = -1.0;
+    for (int a = 0; a < ntypes; ++a) {
+        for (int b = 0; b < ntypes; ++b) {
+            const float rc = rcut[a * ntypes + b];
+            if (isnan(rc) || rc != rcut[b * ntypes + a]) return QBVH_EINVAL;
+            if (!isfinite(rc) && rc > 0) return QBVH_EINVAL;
+            if (rc > 0.0f) {
+                const double r = (double)rc + (double)skin;
+                rlist2[a * QBVH_MAX_TYPES + b] = r * r;
+                rmax = r > rmax ? r : rmax;
+            }
+        }
+    }
+    const double lmin = fmin((double)box[0], fmin((double)box[1], (double)box[2]));
+    if (!(2.0 * rmax * (1.0 + 1e-9) < lmin)) return QBVH_EGEOM;
+    return QBVH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qbvh_strerror(int code) {
+    switch (code) {
+    case QBVH_OK: return "ok";
+    case QBVH_EINVAL: return "invalid argument";
+    case QBVH_EGEOM: return "list radius too large for the box (minimum image not unique)";
+    case QBVH_ENOMEM: return "out of device memory";
+    case QBVH_EHIP: return "HIP runtime error";
+    case QBVH_EAGAIN: return "request does not fit the server budget now";
+    case QBVH_ENOTSUP: return "not supported";
+    default: return "unknown error";
+    }
+}
+
+int qbvh_last_hip_error(void) { return g_last_hip_error; }
+
+size_t qbvh_workspace_bytes(int32_t n, int32_t ntypes, const qbvh_opts_t *opts) {
+    qbvh_opts_t o;
+    if (n < 0 || n > kMaxParticles || ntypes < 1 || ntypes > QBVH_MAX_TYPES || resolve_opts(opts, &o) != QBVH_OK)
+        return 0;
+    return qbi::workspace_bytes(n);
+}
+
+void qbvh_free(qbvh_t *tree) {
+    if (!tree) return;
+    if (tree->ws.base) (void)hipFree(tree->ws.base);
+    delete tree;
+}
+
+int qbvh_build(qbvh_t **tree, const float *d_pos, const int32_t *d_type, int32_t n, int32_t ntypes,
+               const float box[3], const qbvh_opts_t *opts, qbvh_stream_t stream) {
+    if (!tree || n < 0 || n > kMaxParticles || ntypes < 1 || ntypes > QBVH_MAX_TYPES || !box_ok(box))
+        return QBVH_EINVAL;
+    if (n > 0 && !d_pos) return QBVH_EINVAL;
+    if (n > 0 && ntypes > 1 && !d_type) return QBVH_EINVAL;
+    qbvh_opts_t o;
+    int rc = resolve_opts(opts, &o);
+    if (rc != QBVH_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+
+    qbvh_t *t = *tree;
+    const bool fresh = (t == nullptr);
+    if (fresh) {
+        t = new (std::nothrow) qbvh_t();
+        if (!t) return QBVH_ENOMEM;
+    }
+    if (t->ws.base == nullptr || t->ws.cap < n) {
+        if (t->ws.base) {
+            hipError_t e = hipStreamSynchronize(t->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                if (fresh) delete t;
+                return hip_fail(e);
+            }
+            (void)hipFree(t->ws.base);
+            t->ws = Workspace{};
+        }
+        const int32_t cap = n > 0 ? n : 1;
+        void *base = nullptr;
+        hipError_t e = hipMalloc(&base, qbi::workspace_bytes(cap));
+        if (e != hipSuccess) {
+            if (fresh) delete t;
+            else t->ws = Workspace{};
+            return hip_fail(e);
+        }
+        qbi::workspace_carve(t->ws, base, cap);
+    }
+    t->n = n;
+    t->ntypes = ntypes;
+    memcpy(t->box, box, sizeof(t->box));
+    t->opts = o;
+    t->stream = s;
+    *tree = t;
+
+    hipError_t e = qbi::launch_build(t->ws, d_pos, ntypes > 1 ? d_type : nullptr, n, ntypes, box, o.leaf_size,
+                                      o.qbits, o.validate, s);
+    if (e != hipSuccess) return hip_fail(e);
+    if (o.validate) {
+        int32_t err = 0;
+        e = hipMemcpyAsync(&err, t->ws.err, sizeof(err), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e);
+        if (err) return QBVH_EINVAL;
+    }
+    return QBVH_OK;
+}
+
+int nlist_build(const qbvh_t *tree, const float *rcut, float skin, int32_t max_nbr, int32_t *d_nbr,
+                int32_t *d_count, int32_t *d_overflow, qbvh_stream_t stream) {
+    if (!tree || max_nbr < 0 || !d_overflow) return QBVH_EINVAL;
+    if (tree->n > 0 && (!d_count || (max_nbr > 0 && !d_nbr))) return QBVH_EINVAL;
+    qbi::TravArgs a{};
+    int rc = list_radii(rcut, skin, tree->ntypes, tree->box, a.rlist2);
+    if (rc != QBVH_OK) return rc;
+    a.slots = tree->ws.slots;
+    a.sorted = tree->ws.sorted;
+    a.meta = tree->ws.meta;
+    a.nbr = d_nbr;
+    a.count = d_count;
+    a.overflow = d_overflow;
+    for (int d = 0; d < 3; ++d) {
+        a.L[d] = (double)tree->box[d];
+        a.Lf[d] = tree->box[d];
+    }
+    a.lmax = fmax(a.L[0], fmax(a.L[1], a.L[2]));
+    a.n = tree->n;
+    a.ntypes = tree->ntypes;
+    a.max_nbr = max_nbr;
+    const bool vec4 = max_nbr > 0 && (max_nbr % 4) == 0 && (((uintptr_t)d_nbr) & 15u) == 0;
+    hipError_t e = qbi::launch_traverse(a, tree->opts.block_size, vec4, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return QBVH_OK;
+}
+
+int qbvh_info(const qbvh_t *tree, qbvh_info_t *info) {
+    if (!tree || !info) return QBVH_EINVAL;
+    memset(info, 0, sizeof(*info));
+    info->n = tree->n;
+    info->ntypes = tree->ntypes;
+    info->leaf_size = tree->opts.leaf_size;
+    info->qbits = tree->opts.qbits;
+    if (!tree->ws.base) return QBVH_OK;
+    TreeMeta m[QBVH_MAX_TYPES];
+    hipError_t e = hipStreamSynchronize(tree->stream);
+    if (e == hipSuccess) e = hipMemcpy(m, tree->ws.meta, sizeof(TreeMeta) * tree->ntypes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    int32_t nslots = 0;
+    for (int t = 0; t < tree->ntypes; ++t) {
+        info->tree_start[t] = m[t].start;
+        info->tree_count[t] = m[t].count;
+        info->tree_root[t] = m[t].root;
+        info->tree_end[t] = m[t].end;
+        for (int d = 0; d < 3; ++d) {
+            info->root_lo[t][d] = m[t].lo[d];
+            info->root_hi[t][d] = m[t].hi[d];
+        }
+        info->h[t] = m[t].h;
+        nslots = m[t].end > nslots ? m[t].end : nslots;
+    }
+    info->nslots = tree->n > 0 ? nslots : 0;
+    return QBVH_OK;
+}
+
+int qbvh_export(const qbvh_t *tree, int32_t what, void *d_dst, size_t dst_bytes, qbvh_stream_t stream) {
+    if (!tree || !d_dst) return QBVH_EINVAL;
+    const Workspace &w = tree->ws;
+    const size_t n = (size_t)tree->n;
+    const void *src = nullptr;
+    size_t bytes = 0;
+    switch (what) {
+    case QBVH_EXPORT_KEYS: src = w.keys; bytes = n * 4; break;
+    case QBVH_EXPORT_PERM: src = w.vals; bytes = n * 4; break;
+    case QBVH_EXPORT_SORTED: src = w.sorted; bytes = n * 16; break;
+    case QBVH_EXPORT_LEFT: src = w.left; bytes = n * 4; break;
+    case QBVH_EXPORT_RIGHT: src = w.right; bytes = n * 4; break;
+    case QBVH_EXPORT_RANGE_F: src = w.rf; bytes = n * 4; break;
+    case QBVH_EXPORT_RANGE_L: src = w.rl; bytes = n * 4; break;
+    case QBVH_EXPORT_PARENT: src = w.parent; bytes = n * 4; break;
+    case QBVH_EXPORT_LEAF_PARENT: src = w.leaf_parent; bytes = n * 4; break;
+    case QBVH_EXPORT_BOX_LO: src = w.box_lo; bytes = n * 16; break;
+    case QBVH_EXPORT_BOX_HI: src = w.box_hi; bytes = n * 16; break;
+    case QBVH_EXPORT_SLOTS: src = w.slots; bytes = (n > 0 ? 2 * n - 1 : 0) * 16; break;
+    default: return QBVH_EINVAL;
+    }
+    if (bytes > dst_bytes) bytes = dst_bytes;
+    if (bytes == 0 || !src) return QBVH_OK;
+    hipError_t e = hipMemcpyAsync(d_dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return QBVH_OK;
+}
+
+// Batched form: every system is built and traversed in stream order using a
+// pool of per-system handles kept by the library.
+int nlist_build_many(int32_t nsys, const qbvh_system_t *sys, const qbvh_batch_opts_t *opts, qbvh_stream_t stream) {
+    static thread_local std::vector<qbvh_t *> pool;
+    if (nsys < 0 || (nsys > 0 && !sys)) return QBVH_EINVAL;
+    qbvh_opts_t o{};
+    if (opts) {
+        o.leaf_size = opts->leaf_size;
+        o.qbits = opts->qbits;
+        o.block_size = opts->block_size;
+    }
+    for (int32_t i = 0; i < nsys; ++i) {
+        const qbvh_system_t &y = sys[i];
+        double r2[QBVH_MAX_TYPES * QBVH_MAX_TYPES];
+        if (y.ntypes < 1 || y.ntypes > QBVH_MAX_TYPES || !box_ok(y.box)) return QBVH_EINVAL;
+        int rc = list_radii(y.rcut, y.skin, y.ntypes, y.box, r2);
+        if (rc != QBVH_OK) return rc;
+    }
+    if ((int32_t)pool.size() < nsys) pool.resize(nsys, nullptr);
+    for (int32_t i = 0; i < nsys; ++i) {
+        const qbvh_system_t &y = sys[i];
+        int rc = qbvh_build(&pool[i], y.d_pos, y.d_type, y.n, y.ntypes, y.box, &o, stream);
+        if (rc != QBVH_OK) return rc;
+        rc = nlist_build(pool[i], y.rcut, y.skin, y.max_nbr, y.d_nbr, y.d_count, y.d_overflow, stream);
+        if (rc != QBVH_OK) return rc;
+    }
+    return QBVH_OK;
+}
+
+}  // extern "C"

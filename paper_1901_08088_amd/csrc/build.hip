@@ -1,0 +1,396 @@
+// Tree build: Morton codes, Z-order sort, Karras radix tree, bottom-up boxes,
+// quantized rope-linked node layout (Section 2.1 and Section 2.2, Fig. 3).
+//
+// Layout written here (16-byte slots, depth-first preorder per type tree):
+//   internal node: w_d = q_lo_d | (q_hi_d << 16) for d = x, y, z; w_3 = rope
+//   particle:      w_0..w_2 = fp32 bits of x, y, z; w_3 = ~original index
+// The left child of an internal node is the next slot and a particle's rope is
+// the next slot, so only the rope of an internal node is stored.  A subtree of
+// at most `leaf_size` particles is stored as that many particle slots.
+//
+// Slot positions come from one scan instead of a top-down walk.  With C[f] the
+// number of kept internal nodes whose particle range starts at sorted position
+// f and P its exclusive scan:
+//   particle k        -> slot k + P[k + 1]
+//   kept node [f, l]  -> slot f + P[f] + (number of its ancestors that share f)
+//   rope of [f, l]    -> slot (l + 1) + P[l + 1]
+// because in preorder the slots before a node are the particles before f, the
+// kept nodes starting before f, and its ancestors starting at f.
+#include "qbvh_internal.h"
+
+namespace qbi {
+namespace {
+
+constexpr int kBuildThreads = 256;
+constexpr int kMaxDepth = 128;  // > 65, the deepest possible radix tree over 64-bit keys
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// Bin of one coordinate: floor(x * (1023 / L)) in fp64, clamped to [0, 1023].
+__device__ __forceinline__ uint32_t morton_bin(float x, double scale) {
+    double b = floor((double)x * scale);
+    if (!(b >= 0.0)) b = 0.0;  // negative or NaN
+    if (b > 1023.0) b = 1023.0;
+    return (uint32_t)b;
+}
+
+struct Segment {
+    int32_t s, e;
+};
+
+__device__ __forceinline__ Segment segment_of(uint32_t key, int32_t n, int32_t ntypes,
+                                              const uint32_t *__restrict__ type_count) {
+    if (ntypes == 1) return {0, n};
+    const uint32_t t = key >> 30;
+    int32_t s = 0;
+    for (uint32_t u = 0; u < t; ++u) s += (int32_t)type_count[u];
+    return {s, s + (int32_t)type_count[t]};
+}
+
+__global__ __launch_bounds__(kBuildThreads) void k_init(uint32_t *type_count, int32_t *err) {
+    if (threadIdx.x < QBVH_MAX_TYPES) type_count[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *err = 0;
+}
+
+__global__ __launch_bounds__(kBuildThreads) void k_morton(const float *__restrict__ pos,
+                                                          const int32_t *__restrict__ type, int32_t n,
+                                                          int32_t ntypes, float Lx, float Ly, float Lz,
+                                                          double sx, double sy, double sz, int32_t validate,
+                                                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                          uint32_t *__restrict__ kept,
+                                                          uint32_t *__restrict__ type_count, int32_t *err) {
+    __shared__ uint32_t s_cnt[QBVH_MAX_TYPES];
+    const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
+    if (threadIdx.x < QBVH_MAX_TYPES) s_cnt[threadIdx.x] = 0;
+    if (k <= n) kept[k] = 0;
+    __syncthreads();
+    if (k < n) {
+        const float x = pos[3 * (int64_t)k + 0];
+        const float y = pos[3 * (int64_t)k + 1];
+        const float z = pos[3 * (int64_t)k + 2];
+        int32_t t = type ? type[k] : 0;
+        if (validate) {
+            bool ok = (x >= 0.0f && x < Lx) && (y >= 0.0f && y < Ly) && (z >= 0.0f && z < Lz) &&
+                      (t >= 0 && t < ntypes);
+            if (!ok) atomicOr(err, 1);
+        }
+        t = t < 0 ? 0 : (t >= ntypes ? ntypes - 1 : t);
+        const uint32_t code = spread10(morton_bin(x, sx)) | (spread10(morton_bin(y, sy)) << 1) |
+                              (spread10(morton_bin(z, sz)) << 2);
+        keys[k] = code | ((uint32_t)t << 30);
+        vals[k] = (uint32_t)k;
+        if (ntypes > 1) atomicAdd(&s_cnt[t], 1u);
+    }
+    __syncthreads();
+    if (ntypes > 1 && threadIdx.x < (unsigned)ntypes && s_cnt[threadIdx.x])
+        atomicAdd(&type_count[threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(kBuildThreads) void k_gather(const float *__restrict__ pos,
+                                                          const uint32_t *__restrict__ vals, int32_t n,
+                                                          float4 *__restrict__ sorted) {
+    const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t i = vals[k];
+    float4 p;
+    p.x = pos[3 * (int64_t)i + 0];
+    p.y = pos[3 * (int64_t)i + 1];
+    p.z = pos[3 * (int64_t)i + 2];
+    p.w = __int_as_float(~(int32_t)i);
+    sorted[k] = p;
+}
+
+// Common-prefix length of the augmented keys (key << 32 | position); -1
+// outside the segment.  Equal keys are told apart by position (Karras's rule).
+__device__ __forceinline__ int delta(const uint32_t *__restrict__ keys, int32_t i, int32_t j, Segment g) {
+    if (j < g.s || j >= g.e) return -1;
+    const uint32_t a = keys[i], b = keys[j];
+    if (a != b) return __clz(a ^ b);
+    return 32 + __clz((uint32_t)(i ^ j));
+}
+
+// Karras's parallel construction: internal node i of a segment covers a
+// range with i at one end; its direction, far end and split are found by
+// exponential then binary search on the common-prefix length.
+__global__ __launch_bounds__(kBuildThreads) void k_karras(const uint32_t *__restrict__ keys, int32_t n,
+                                                          int32_t ntypes, const uint32_t *__restrict__ type_count,
+                                                          int32_t leaf_size, int32_t *__restrict__ left,
+                                                          int32_t *__restrict__ right, int32_t *__restrict__ rf,
+                                                          int32_t *__restrict__ rl, int32_t *__restrict__ parent,
+                                                          int32_t *__restrict__ leaf_parent,
+                                                          uint32_t *__restrict__ visit, uint32_t *__restrict__ kept) {
+    const int32_t i = blockIdx.x * kBuildThreads + threadIdx.x;
+    if (i >= n) return;
+    const Segment g = segment_of(keys[i], n, ntypes, type_count);
+    visit[i] = 0;
+    if (i == g.e - 1) {  // no internal node carries the last position's id
+        if (g.e - g.s == 1) leaf_parent[i] = -1;
+        return;
+    }
+    const int d = (delta(keys, i, i + 1, g) - delta(keys, i, i - 1, g)) > 0 ? 1 : -1;
+    const int dmin = delta(keys, i, i - d, g);
+    int32_t lmax = 2;
+    while (delta(keys, i, i + lmax * d, g) > dmin) lmax <<= 1;
+    int32_t l = 0;
+    for (int32_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (delta(keys, i, i + (l + t) * d, g) > dmin) l += t;
+    const int32_t j = i + l * d;
+    const int dnode = delta(keys, i, j, g);
+    int32_t s = 0;
+    int32_t t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (delta(keys, i, i + (s + t) * d, g) > dnode) s += t;
+    } while (t > 1);
+    const int32_t gamma = i + s * d + (d < 0 ? -1 : 0);
+    const int32_t f = i < j ? i : j;
+    const int32_t la = i < j ? j : i;
+    const int32_t cl = (f == gamma) ? ~gamma : gamma;
+    const int32_t cr = (la == gamma + 1) ? ~(gamma + 1) : gamma + 1;
+    left[i] = cl;
+    right[i] = cr;
+    rf[i] = f;
+    rl[i] = la;
+    if (cl < 0) leaf_parent[gamma] = i; else parent[gamma] = i;
+    if (cr < 0) leaf_parent[gamma + 1] = i; else parent[gamma + 1] = i;
+    if (i == g.s) parent[i] = -1;
+    if (la - f + 1 > leaf_size) atomicAdd(&kept[f], 1u);
+}
+
+// Bottom-up boxes: every leaf climbs; at each internal node the first arrival
+// stops and the second merges both children and continues.  The visit
+// counter is an agent-scope acquire-release atomic so the sibling's box,
+// written before its own arrival, is visible to the merging thread.
+__global__ __launch_bounds__(kBuildThreads) void k_fit(const float4 *__restrict__ sorted,
+                                                       const int32_t *__restrict__ left,
+                                                       const int32_t *__restrict__ right,
+                                                       const int32_t *__restrict__ parent,
+                                                       const int32_t *__restrict__ leaf_parent, uint32_t *visit,
+                                                       float4 *box_lo, float4 *box_hi, int32_t n) {
+    const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
+    if (k >= n) return;
+    int32_t p = leaf_parent[k];
+    // Each level of the radix tree consumes at least one bit of the 64-bit
+    // augmented key, so no climb is longer than 65 steps; the bound only
+    // guarantees termination.
+    for (int step = 0; p >= 0 && step < kMaxDepth; ++step) {
+        const uint32_t old = __hip_atomic_fetch_add(&visit[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0) return;
+        const int32_t c0 = left[p], c1 = right[p];
+        float4 alo, ahi, blo, bhi;
+        if (c0 < 0) {
+            alo = sorted[~c0];
+            ahi = alo;
+        } else {
+            alo = box_lo[c0];
+            ahi = box_hi[c0];
+        }
+        if (c1 < 0) {
+            blo = sorted[~c1];
+            bhi = blo;
+        } else {
+            blo = box_lo[c1];
+            bhi = box_hi[c1];
+        }
+        box_lo[p] = make_float4(fminf(alo.x, blo.x), fminf(alo.y, blo.y), fminf(alo.z, blo.z), 0.0f);
+        box_hi[p] = make_float4(fmaxf(ahi.x, bhi.x), fmaxf(ahi.y, bhi.y), fmaxf(ahi.z, bhi.z), 0.0f);
+        p = parent[p];
+    }
+}
+
+// Root box, grid spacing and slot range of each type's tree.
+__global__ void k_meta(int32_t n, int32_t ntypes, const uint32_t *__restrict__ type_count,
+                       const float4 *__restrict__ sorted, const float4 *__restrict__ box_lo,
+                       const float4 *__restrict__ box_hi, const uint32_t *__restrict__ P, int32_t qbits,
+                       double ext_floor, TreeMeta *__restrict__ meta) {
+    const int t = threadIdx.x;
+    if (t >= ntypes) return;
+    int32_t s = 0;
+    for (int u = 0; u < t; ++u) s += (int32_t)type_count[u];
+    const int32_t c = (ntypes == 1) ? n : (int32_t)type_count[t];
+    TreeMeta m;
+    float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
+    if (c == 1) {
+        const float4 p = sorted[s];
+        lo[0] = hi[0] = p.x;
+        lo[1] = hi[1] = p.y;
+        lo[2] = hi[2] = p.z;
+    } else if (c >= 2) {
+        const float4 a = box_lo[s], b = box_hi[s];
+        lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
+        hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
+    }
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        m.lo[d] = lo[d];
+        m.hi[d] = hi[d];
+        const double e = (double)hi[d] - (double)lo[d];
+        ext = e > ext ? e : ext;
+    }
+    ext = ext > ext_floor ? ext : ext_floor;
+    m.h = ext / (double)((1 << qbits) - 1);
+    m.inv_h = 1.0 / m.h;
+    m.start = s;
+    m.count = c;
+    m.root = s + (int32_t)P[s];
+    m.end = (s + c) + (int32_t)P[s + c];
+    m.pad[0] = m.pad[1] = 0;
+    meta[t] = m;
+}
+
+__device__ __forceinline__ uint32_t quantize_lo(float v, float root, double h, uint32_t qmax) {
+    double q = floor(((double)v - (double)root) / h);
+    if (!(q >= 0.0)) q = 0.0;
+    if (q > (double)qmax) q = (double)qmax;
+    return (uint32_t)q;
+}
+
+__device__ __forceinline__ uint32_t quantize_hi(float v, float root, double h, uint32_t qmax) {
+    double q = ceil(((double)v - (double)root) / h);
+    if (!(q >= 0.0)) q = 0.0;
+    if (q > (double)qmax) q = (double)qmax;
+    return (uint32_t)q;
+}
+
+// Write every slot: particle k always, internal node k when it exists and is kept.
+__global__ __launch_bounds__(kBuildThreads) void k_emit(int32_t n, int32_t ntypes,
+                                                        const uint32_t *__restrict__ keys,
+                                                        const uint32_t *__restrict__ type_count,
+                                                        const float4 *__restrict__ sorted,
+                                                        const int32_t *__restrict__ left,
+                                                        const int32_t *__restrict__ rf, const int32_t *__restrict__ rl,
+                                                        const int32_t *__restrict__ parent,
+                                                        const float4 *__restrict__ box_lo,
+                                                        const float4 *__restrict__ box_hi,
+                                                        const uint32_t *__restrict__ P,
+                                                        const TreeMeta *__restrict__ meta, int32_t leaf_size,
+                                                        int32_t qbits, uint4 *__restrict__ slots) {
+    const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
+    if (k >= n) return;
+    const float4 p = sorted[k];
+    slots[k + (int32_t)P[k + 1]] =
+        make_uint4(__float_as_uint(p.x), __float_as_uint(p.y), __float_as_uint(p.z), __float_as_uint(p.w));
+
+    const uint32_t key = keys[k];
+    const Segment g = segment_of(key, n, ntypes, type_count);
+    if (k >= g.e - 1) return;  // not an internal node id
+    const int32_t f = rf[k], l = rl[k];
+    if (l - f + 1 <= leaf_size) return;  // collapsed into particle slots
+    int32_t rank = 0;
+    int32_t u = k;
+    for (int step = 0; step < kMaxDepth; ++step) {
+        const int32_t pp = parent[u];
+        if (pp < 0 || left[pp] != u) break;
+        ++rank;
+        u = pp;
+    }
+    const int32_t at = f + (int32_t)P[f] + rank;
+    const int32_t rope = (l + 1) + (int32_t)P[l + 1];
+    const TreeMeta &m = meta[ntypes == 1 ? 0 : (key >> 30)];
+    const uint32_t qmax = (1u << qbits) - 1u;
+    const float4 lo = box_lo[k], hi = box_hi[k];
+    const uint32_t wx = quantize_lo(lo.x, m.lo[0], m.h, qmax) | (quantize_hi(hi.x, m.lo[0], m.h, qmax) << 16);
+    const uint32_t wy = quantize_lo(lo.y, m.lo[1], m.h, qmax) | (quantize_hi(hi.y, m.lo[1], m.h, qmax) << 16);
+    const uint32_t wz = quantize_lo(lo.z, m.lo[2], m.h, qmax) | (quantize_hi(hi.z, m.lo[2], m.h, qmax) << 16);
+    slots[at] = make_uint4(wx, wy, wz, (uint32_t)rope);
+}
+
+inline dim3 grid_for(int64_t items) { return dim3((unsigned)((items + kBuildThreads - 1) / kBuildThreads)); }
+
+}  // namespace
+
+size_t workspace_bytes(int32_t cap) {
+    const size_t c = cap > 0 ? (size_t)cap : 1;
+    const size_t tiles = (size_t)radix_tiles((int32_t)c);
+    const size_t sb = (size_t)scan_blocks((int32_t)c + 1) + 1;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t b = 0;
+    b += 4 * al(c * 4);                       // keys, vals, keys2, vals2
+    b += al(256 * tiles * 4) + al(256 * 4);   // histograms
+    b += al(c * 16);                          // sorted
+    b += 6 * al(c * 4);                       // left right rf rl parent leaf_parent
+    b += al(c * 4);                           // visit
+    b += 2 * al(c * 16);                      // boxes
+    b += al((c + 1) * 4) + al(sb * 4);        // kept + scan partials
+    b += al(2 * c * 16);                      // slots
+    b += al(QBVH_MAX_TYPES * sizeof(TreeMeta)) + al(QBVH_MAX_TYPES * 4) + al(4);
+    return b;
+}
+
+void workspace_carve(Workspace &w, void *base, int32_t cap) {
+    const size_t c = cap > 0 ? (size_t)cap : 1;
+    const size_t tiles = (size_t)radix_tiles((int32_t)c);
+    const size_t sb = (size_t)scan_blocks((int32_t)c + 1) + 1;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char *p = (char *)base;
+    auto take = [&](size_t bytes) {
+        void *r = p;
+        p += al(bytes);
+        return r;
+    };
+    w.cap = cap;
+    w.tiles = (int32_t)tiles;
+    w.base = base;
+    w.keys = (uint32_t *)take(c * 4);
+    w.vals = (uint32_t *)take(c * 4);
+    w.keys2 = (uint32_t *)take(c * 4);
+    w.vals2 = (uint32_t *)take(c * 4);
+    w.hist = (uint32_t *)take(256 * tiles * 4);
+    w.digit_total = (uint32_t *)take(256 * 4);
+    w.sorted = (float4 *)take(c * 16);
+    w.left = (int32_t *)take(c * 4);
+    w.right = (int32_t *)take(c * 4);
+    w.rf = (int32_t *)take(c * 4);
+    w.rl = (int32_t *)take(c * 4);
+    w.parent = (int32_t *)take(c * 4);
+    w.leaf_parent = (int32_t *)take(c * 4);
+    w.visit = (uint32_t *)take(c * 4);
+    w.box_lo = (float4 *)take(c * 16);
+    w.box_hi = (float4 *)take(c * 16);
+    w.kept = (uint32_t *)take((c + 1) * 4);
+    w.scan_part = (uint32_t *)take(sb * 4);
+    w.slots = (uint4 *)take(2 * c * 16);
+    w.meta = (TreeMeta *)take(QBVH_MAX_TYPES * sizeof(TreeMeta));
+    w.type_count = (uint32_t *)take(QBVH_MAX_TYPES * 4);
+    w.err = (int32_t *)take(4);
+    w.bytes = (size_t)(p - (char *)base);
+}
+
+hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d_type, int32_t n, int32_t ntypes,
+                        const float box[3], int32_t leaf_size, int32_t qbits, int32_t validate, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, w.type_count, w.err);
+    const double sx = 1023.0 / (double)box[0];
+    const double sy = 1023.0 / (double)box[1];
+    const double sz = 1023.0 / (double)box[2];
+    hipLaunchKernelGGL(k_morton, grid_for((int64_t)n + 1), dim3(kBuildThreads), 0, s, d_pos, d_type, n, ntypes,
+                       box[0], box[1], box[2], sx, sy, sz, validate, w.keys, w.vals, w.kept, w.type_count, w.err);
+    hipError_t e = launch_radix_sort(w.keys, w.vals, w.keys2, w.vals2, w.hist, w.digit_total, n, w.tiles, s);
+    if (e != hipSuccess) return e;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_gather, grid_for(n), dim3(kBuildThreads), 0, s, d_pos, w.vals, n, w.sorted);
+        hipLaunchKernelGGL(k_karras, grid_for(n), dim3(kBuildThreads), 0, s, w.keys, n, ntypes, w.type_count,
+                           leaf_size, w.left, w.right, w.rf, w.rl, w.parent, w.leaf_parent, w.visit, w.kept);
+        hipLaunchKernelGGL(k_fit, grid_for(n), dim3(kBuildThreads), 0, s, w.sorted, w.left, w.right, w.parent,
+                           w.leaf_parent, w.visit, w.box_lo, w.box_hi, n);
+    }
+    e = launch_exclusive_scan(w.kept, n + 1, w.scan_part, s);
+    if (e != hipSuccess) return e;
+    const double lmax = (double)fmaxf(box[0], fmaxf(box[1], box[2]));
+    const double ext_floor = lmax * 0x1p-24;
+    hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, s, n, ntypes, w.type_count, w.sorted, w.box_lo, w.box_hi,
+                       w.kept, qbits, ext_floor, w.meta);
+    if (n > 0)
+        hipLaunchKernelGGL(k_emit, grid_for(n), dim3(kBuildThreads), 0, s, n, ntypes, w.keys, w.type_count,
+                           w.sorted, w.left, w.rf, w.rl, w.parent, w.box_lo, w.box_hi, w.kept, w.meta, leaf_size,
+                           qbits, w.slots);
+    return hipGetLastError();
+}
+
+}  // namespace qbi

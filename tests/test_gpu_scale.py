@@ -1,0 +1,46 @@
+"""Parity at the full sizes of the Lennard-Jones workloads (N = 1M and 8M,
+density 0.85, rc 3.0 + skin 0.4, max_nbr 256), in the launch configuration the
+benchmark times: every count against the oracle's cell list, and complete rows
+for a seeded sample of particles."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1901_08088_amd as Q
+import workloads as W
+
+from nlist_check import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+BENCH_OPTS = {"leaf_size": 1, "qbits": 16, "block_size": 256}
+
+
+@pytest.mark.parametrize("n", [1_000_000, 8_000_000])
+def test_lj_fluid_full_size(n):
+    torch = require_gpu()
+    cfg = W.lj_fluid(n)
+    print(f"[scale] N={n} L={cfg.box[0]:.4f}", flush=True)
+    pos = torch.from_numpy(cfg.pos).cuda()
+    tree = Q.qbvh_build(pos, None, cfg.box, 1, BENCH_OPTS)
+    max_nbr = 256
+    nbr = torch.empty((n, max_nbr), dtype=torch.int32, device="cuda")
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    ovf = torch.empty(1, dtype=torch.int32, device="cuda")
+    Q.nlist_build(tree, cfg.rcut, cfg.skin, max_nbr, nbr, cnt, ovf)
+    torch.cuda.synchronize()
+    gcnt = cnt.cpu().numpy().astype(np.int64)
+    ocnt = oracle.neighbor_counts(cfg.pos, cfg.box, cfg.rcut, cfg.skin)
+    bad = np.nonzero(gcnt != ocnt)[0]
+    assert bad.size == 0, f"{bad.size} count mismatches, first {bad[:5].tolist()}"
+    assert int(ovf.item()) == int((ocnt > max_nbr).any())
+    # complete rows for a sample, including the particles nearest the box faces
+    rng = np.random.default_rng(n)
+    face = np.argsort(np.min(np.minimum(cfg.pos, cfg.box - cfg.pos), axis=1))[:500]
+    sample = np.unique(np.concatenate([rng.choice(n, 3000, replace=False), face]))
+    rows = nbr[torch.from_numpy(sample).cuda()].cpu().numpy()
+    rp, cols = oracle.neighbor_lists(cfg.pos, cfg.box, cfg.rcut, cfg.skin, queries=sample)
+    for q, i in enumerate(sample):
+        c = gcnt[i]
+        assert sorted(rows[q, :c].tolist()) == cols[rp[q]:rp[q + 1]].tolist(), i
+    print(f"[scale] N={n} pairs={int(gcnt.sum())} mean={gcnt.mean():.3f} ok", flush=True)
