@@ -43,11 +43,12 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def traversal_bytes(n: int, nslots: int, stored_pairs: int) -> int:
-    """Algorithmic HBM bytes of one traversal launch: every query record (16 B)
-    read once, every slot (16 B) read once, every stored neighbor index (4 B)
-    and every count (4 B) written once."""
-    return 16 * n + 16 * nslots + 4 * stored_pairs + 4 * n
+def traversal_bytes(n: int, nrecords: int, stored_pairs: int) -> int:
+    """Algorithmic HBM bytes of one traversal launch: the Z-ordered particle
+    array (16 B per particle, queries and candidates alike) read once, every
+    record (32 B) and its rope (4 B) read once, every stored neighbor index
+    (4 B) and every count (4 B) written once."""
+    return 16 * n + 36 * nrecords + 4 * stored_pairs + 4 * n
 
 
 def cpu_baseline(cfg, sample_rows: int) -> dict:
@@ -134,7 +135,7 @@ def main(argv=None) -> int:
     pairs = int(counts.sum())
     stored = int(np.minimum(counts, max_nbr).sum())
     info = Q.qbvh_info(tree)
-    tbytes = traversal_bytes(n, info["nslots"], stored)
+    tbytes = traversal_bytes(n, info["nrecords"], stored)
     achieved = tbytes / (trav_ms * 1e-3) / 1e9
     builds_per_s = args.steps / wall
     log(f"build {build_ms:.3f} ms, traversal {trav_ms:.3f} ms, {ms_per_step:.3f} ms/step, "

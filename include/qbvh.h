@@ -59,7 +59,7 @@ typedef void *qbvh_stream_t;  /* hipStream_t */
 
 enum {
     QBVH_OK = 0,
-    QBVH_EINVAL = -1, /* bad argument: NULL pointer, n < 0, ntypes outside 1..4,
+    QBVH_EINVAL = -1, /* bad argument: NULL pointer, n outside 0..2^28-1, ntypes outside 1..4,
                          box edge <= 0 or not finite, skin < 0, rcut not symmetric,
                          max_nbr < 0, unsupported option value, or (with
                          validate) a coordinate outside [0, L) or a type outside
@@ -77,8 +77,9 @@ enum {
 /* Build options.  A NULL pointer, or a zero field, selects the default. */
 typedef struct {
     int32_t leaf_size;  /* particles per leaf run: a subtree with at most this many
-                           particles is stored as consecutive particle slots
-                           (1..32, default 1 = one particle per leaf as in the paper) */
+                           particles is not split further and its particles are
+                           tested one by one (1..8, default 1 = one particle per
+                           leaf as in the paper) */
     int32_t qbits;      /* grid bits per axis for the quantized bounds (8..16,
                            default 16; the paper's layout uses 10) */
     int32_t block_size; /* traversal workgroup size: 64, 128, 192 or 256
@@ -99,7 +100,7 @@ typedef struct {
  *   d_pos   device float [n][3], x y z of particle i at 3i..3i+2, every
  *           coordinate in [0, box[d]).
  *   d_type  device int32 [n] with values in [0, ntypes), or NULL when ntypes == 1.
- *   n       number of particles (0 is allowed: an empty tree, no work).
+ *   n       number of particles, 0 .. 2^28 - 1 (0: an empty tree, no work).
  *   ntypes  1..4; one tree is built per type (types with no particles give
  *           empty trees).
  *   box     host float [3]: orthorhombic periodic box edges, all > 0.
@@ -184,11 +185,12 @@ QBVH_API size_t qbvh_workspace_bytes(int32_t n, int32_t ntypes, const qbvh_opts_
 
 /* Host-side summary of a built tree.  Synchronizes the handle's last stream. */
 typedef struct {
-    int32_t n, ntypes, nslots, leaf_size, qbits;
+    int32_t n, ntypes, nrecords, leaf_size, qbits;
     int32_t tree_start[QBVH_MAX_TYPES]; /* first sorted index of each type */
     int32_t tree_count[QBVH_MAX_TYPES]; /* particles of each type */
-    int32_t tree_root[QBVH_MAX_TYPES];  /* slot index of each tree's root */
-    int32_t tree_end[QBVH_MAX_TYPES];   /* one past each tree's last slot */
+    int32_t tree_root[QBVH_MAX_TYPES];  /* root record of each tree, or (trees of at most
+                                           leaf_size particles) the run reference below */
+    int32_t tree_end[QBVH_MAX_TYPES];   /* one past each tree's last record */
     float root_lo[QBVH_MAX_TYPES][3];   /* root-node box of each tree */
     float root_hi[QBVH_MAX_TYPES][3];
     double h[QBVH_MAX_TYPES];           /* grid spacing of each tree */
@@ -210,7 +212,12 @@ enum {
     QBVH_EXPORT_LEAF_PARENT = 9, /* int32 [n] parent of leaf k (-1 for a one-particle tree) */
     QBVH_EXPORT_BOX_LO = 10, /* float4 [n]  lower box corner of internal node i */
     QBVH_EXPORT_BOX_HI = 11, /* float4 [n]  upper box corner of internal node i */
-    QBVH_EXPORT_SLOTS = 12   /* uint32 [nslots][4] quantized node / particle slots */
+    QBVH_EXPORT_RECORDS = 12, /* uint32 [nrecords][8] two-wide quantized records:
+                                 words 0-2 left child box, 3-5 right child box
+                                 (q_lo | q_hi << 16 per axis), 6 left child,
+                                 7 right child: record index, or a particle run
+                                 ~((first << 3) | (count - 1)) */
+    QBVH_EXPORT_ROPES = 13    /* int32 [nrecords] record that follows each record's subtree */
 };
 /* Internal node ids are sorted positions: the tree of the type occupying
  * sorted positions [s, e) has internal nodes s .. e-2; entries for other ids

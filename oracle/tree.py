@@ -18,11 +18,11 @@ Section 2.2, "Compressed BVH"):
 4. ``node_boxes``    -- axis-aligned box of every internal node, i.e. the
                          min/max over the particles below it (what the
                          bottom-up fit computes).
-5. ``preorder_layout`` -- quantized nodes in a stackless, rope-linked order:
+5. ``record_layout`` -- quantized nodes in a stackless, rope-linked order:
                          bounds snapped to a grid over the root-node box,
                          lower bounds rounded down and upper bounds up, and a
-                         rope per node giving the next node to test when the
-                         node is missed.
+                         rope per node giving the next node to test when
+                         nothing below it needs visiting.
 
 Readings where the paper is silent (listed again in the design notes):
 - One tree per particle type; the type is stored above the 30-bit code
@@ -31,11 +31,16 @@ Readings where the paper is silent (listed again in the design notes):
   where extent is the largest edge of the root-node box (floored at 2^-24 of
   the largest periodic box edge so that a tree of coincident points still has
   a usable grid).  Bounds are stored in 16-bit fields for any b <= 16.
-- The nodes are laid out in depth-first preorder, so the left child of an
-  internal node is the next node and only the rope needs storing; a subtree
-  of at most ``leaf_size`` particles is stored as that many consecutive
-  particle slots (exact fp32 position plus the encoded original index), and a
-  particle slot's rope is implicitly the next slot.
+- Nodes are laid out as two-wide records in depth-first preorder: the record
+  of an internal node holds the quantized boxes of its two children and a
+  reference to each (the record of an internal child, or a run of at most
+  ``leaf_size`` consecutive sorted particles: a subtree that small is not
+  split further), and a separate array holds its rope (the record after its
+  subtree).  The left child's record is the next record.  Testing both child
+  boxes in the parent halves the chain of dependent node loads of a walk.
+- A particle-run reference is ~((first << 3) | (count - 1)), negative; a
+  record reference is the record index, non-negative.  A tree of at most
+  ``leaf_size`` particles has no record: its root is a run.
 """
 from __future__ import annotations
 
@@ -145,56 +150,63 @@ def quantize_box(lo, hi, root_lo, h: float, qbits: int):
     return qlo, qhi
 
 
-def preorder_layout(sorted_pos, sorted_orig, sorted_keys, ntypes: int, box,
-                    leaf_size: int = 1, qbits: int = 16):
-    """Quantized, rope-linked node array for all types' trees.
+def run_ref(first: int, count: int) -> int:
+    """Reference to the particle run [first, first + count) (negative int32)."""
+    return ~((first << 3) | (count - 1))
 
-    Returns (slots uint32 [M, 4], meta list).  Slot formats:
-      internal node:  w_d = q_lo_d | (q_hi_d << 16) for d = x, y, z;
-                      w_3 = rope (index of the slot after this subtree)
-      particle:       w_0..w_2 = fp32 bits of x, y, z; w_3 = ~original index
-    Trees follow each other in type order; ``meta[t]`` holds the tree's first
-    slot (its root), one past its last slot, its root box and grid spacing.
+
+def record_layout(sorted_pos, sorted_keys, ntypes: int, box, leaf_size: int = 1, qbits: int = 16):
+    """Two-wide quantized records for all types' trees.
+
+    Returns (records uint32 [M, 8], ropes int32 [M], meta list).  Record of
+    internal node v with children a (left) and b (right):
+      words 0-2: box of a, w_d = q_lo_d | (q_hi_d << 16) for d = x, y, z
+      words 3-5: box of b, same packing
+      word 6:    reference to a;  word 7: reference to b
+    ropes[v] = index of the record that follows v's subtree.  Trees follow
+    each other in type order; ``meta[t]`` holds the tree's root reference,
+    one past its last record, its root box and its grid spacing.
     """
+    assert 1 <= leaf_size <= 8
     p = np.asarray(sorted_pos, dtype=np.float32).reshape(-1, 3)
-    orig = np.asarray(sorted_orig, dtype=np.int64)
-    slots = []
-    meta = []
+    records, ropes, meta = [], [], []
     for t, (s, e) in enumerate(segments(sorted_keys, ntypes)):
-        first = len(slots)
+        first = len(records)
         if e == s:
-            meta.append(dict(start=s, count=0, root=first, end=first, lo=None, hi=None, h=1.0))
+            meta.append(dict(start=s, count=0, root=0, end=first, lo=None, hi=None, h=1.0))
             continue
         tree = radix_tree(sorted_keys, s, e)
         rlo = p[s:e].min(axis=0)
         rhi = p[s:e].max(axis=0)
         h = grid_spacing(rlo, rhi, box, qbits)
-        stack = [("node", s, e - 1)]
-        while stack:
-            item = stack.pop()
-            if item[0] == "close":
-                _, idx, f, l = item
-                lo = p[f:l + 1].min(axis=0)
-                hi = p[f:l + 1].max(axis=0)
-                qlo, qhi = quantize_box(lo, hi, rlo, h, qbits)
-                slots[idx] = [qlo[d] | (qhi[d] << 16) for d in range(3)] + [len(slots)]
-                continue
-            _, f, l = item
-            if l - f + 1 <= leaf_size:
-                for k in range(f, l + 1):
-                    xyz = p[k].view(np.uint32)
-                    slots.append([int(xyz[0]), int(xyz[1]), int(xyz[2]),
-                                  int(np.uint32(np.int64(~orig[k]) & 0xFFFFFFFF))])
-                continue
-            idx = len(slots)
-            slots.append(None)
+        if e - s <= leaf_size:
+            meta.append(dict(start=s, count=e - s, root=run_ref(s, e - s), end=first, lo=rlo, hi=rhi, h=h))
+            continue
+
+        def child_box(f, l):
+            qlo, qhi = quantize_box(p[f:l + 1].min(axis=0), p[f:l + 1].max(axis=0), rlo, h, qbits)
+            return [qlo[d] | (qhi[d] << 16) for d in range(3)]
+
+        def emit(f, l):
+            """Record of node [f, l] in preorder: itself, then its left and right subtrees."""
+            idx = len(records)
             g = tree[(f, l)]
-            stack.append(("close", idx, f, l))
-            stack.append(("node", g + 1, l))
-            stack.append(("node", f, g))
-        meta.append(dict(start=s, count=e - s, root=first, end=len(slots), lo=rlo, hi=rhi, h=h))
-    arr = np.array(slots, dtype=np.uint32).reshape(-1, 4) if slots else np.zeros((0, 4), np.uint32)
-    return arr, meta
+            kids = [(f, g), (g + 1, l)]
+            records.append(child_box(*kids[0]) + child_box(*kids[1]) + [0, 0])
+            ropes.append(-1)
+            for side, (cf, cl) in enumerate(kids):
+                if cl - cf + 1 > leaf_size:
+                    ref = emit(cf, cl)
+                else:
+                    ref = run_ref(cf, cl - cf + 1)
+                records[idx][6 + side] = ref & 0xFFFFFFFF
+            ropes[idx] = len(records)
+            return idx
+
+        emit(s, e - 1)
+        meta.append(dict(start=s, count=e - s, root=first, end=len(records), lo=rlo, hi=rhi, h=h))
+    arr = np.array(records, dtype=np.uint32).reshape(-1, 8) if records else np.zeros((0, 8), np.uint32)
+    return arr, np.array(ropes, dtype=np.int32), meta
 
 
 def build_all(pos, box, types=None, ntypes: int = 1, leaf_size: int = 1, qbits: int = 16):
@@ -205,6 +217,6 @@ def build_all(pos, box, types=None, ntypes: int = 1, leaf_size: int = 1, qbits: 
     segs = segments(skeys, ntypes)
     trees = [radix_tree(skeys, s, e) for (s, e) in segs]
     boxes = [node_boxes(p, tr) for tr in trees]
-    slots, meta = preorder_layout(p, perm, skeys, ntypes, box, leaf_size, qbits)
+    records, ropes, meta = record_layout(p, skeys, ntypes, box, leaf_size, qbits)
     return dict(keys=keys, sorted_keys=skeys, perm=perm, sorted_pos=p, segments=segs,
-                trees=trees, boxes=boxes, slots=slots, meta=meta)
+                trees=trees, boxes=boxes, records=records, ropes=ropes, meta=meta)

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libqbvh.so")
 MAX_TYPES = 4
 OK, EINVAL, EGEOM, ENOMEM, EHIP, EAGAIN, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 EXPORT = dict(keys=1, perm=2, sorted=3, left=4, right=5, range_f=6, range_l=7, parent=8,
-              leaf_parent=9, box_lo=10, box_hi=11, slots=12)
+              leaf_parent=9, box_lo=10, box_hi=11, records=12, ropes=13)
 
 C_API = ("qbvh_build", "nlist_build", "nlist_build_many", "qbvh_free", "qbvh_strerror",
          "qbvh_last_hip_error", "qbvh_workspace_bytes", "qbvh_info", "qbvh_export")
@@ -53,7 +53,7 @@ class QbvhSystem(ctypes.Structure):
 
 
 class QbvhInfo(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("ntypes", ctypes.c_int32), ("nslots", ctypes.c_int32),
+    _fields_ = [("n", ctypes.c_int32), ("ntypes", ctypes.c_int32), ("nrecords", ctypes.c_int32),
                 ("leaf_size", ctypes.c_int32), ("qbits", ctypes.c_int32),
                 ("tree_start", ctypes.c_int32 * MAX_TYPES), ("tree_count", ctypes.c_int32 * MAX_TYPES),
                 ("tree_root", ctypes.c_int32 * MAX_TYPES), ("tree_end", ctypes.c_int32 * MAX_TYPES),
@@ -240,7 +240,7 @@ def qbvh_info(tree: Tree) -> dict:
     info = QbvhInfo()
     _check(lib().qbvh_info(tree.ptr, ctypes.byref(info)), "qbvh_info")
     nt = info.ntypes
-    return dict(n=info.n, ntypes=nt, nslots=info.nslots, leaf_size=info.leaf_size, qbits=info.qbits,
+    return dict(n=info.n, ntypes=nt, nrecords=info.nrecords, leaf_size=info.leaf_size, qbits=info.qbits,
                 tree_start=list(info.tree_start)[:nt], tree_count=list(info.tree_count)[:nt],
                 tree_root=list(info.tree_root)[:nt], tree_end=list(info.tree_end)[:nt],
                 root_lo=[list(info.root_lo[t]) for t in range(nt)],

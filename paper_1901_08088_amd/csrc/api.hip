@@ -38,7 +38,7 @@ int resolve_opts(const qbvh_opts_t *in, qbvh_opts_t *out) {
     if (o.leaf_size == 0) o.leaf_size = 1;
     if (o.qbits == 0) o.qbits = 16;
     if (o.block_size == 0) o.block_size = 256;
-    if (o.leaf_size < 1 || o.leaf_size > 32) return QBVH_EINVAL;
+    if (o.leaf_size < 1 || o.leaf_size > 8) return QBVH_EINVAL;
     if (o.qbits < 8 || o.qbits > 16) return QBVH_EINVAL;
     // the traversal kernel is compiled for at most 256 work-items per group
     if (o.block_size < 64 || o.block_size > 256 || (o.block_size % 64) != 0) return QBVH_EINVAL;
@@ -54,7 +54,8 @@ bool box_ok(const float box[3]) {
     return true;
 }
 
-constexpr int32_t kMaxParticles = (1 << 30) - 1;
+// particle runs store the first sorted position in 28 bits
+constexpr int32_t kMaxParticles = (1 << 28) - 1;
 
 // (rc + skin)^2 in fp64 from the fp32 inputs; -1 marks a pair never listed.
 int list_radii(const float *rcut, float skin, int32_t ntypes, const float box[3],
@@ -176,7 +177,8 @@ int nlist_build(const qbvh_t *tree, const float *rcut, float skin, int32_t max_n
     qbi::TravArgs a{};
     int rc = list_radii(rcut, skin, tree->ntypes, tree->box, a.rlist2);
     if (rc != QBVH_OK) return rc;
-    a.slots = tree->ws.slots;
+    a.records = tree->ws.records;
+    a.ropes = tree->ws.ropes;
     a.sorted = tree->ws.sorted;
     a.meta = tree->ws.meta;
     a.nbr = d_nbr;
@@ -208,7 +210,7 @@ int qbvh_info(const qbvh_t *tree, qbvh_info_t *info) {
     hipError_t e = hipStreamSynchronize(tree->stream);
     if (e == hipSuccess) e = hipMemcpy(m, tree->ws.meta, sizeof(TreeMeta) * tree->ntypes, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e);
-    int32_t nslots = 0;
+    int32_t nrec = 0;
     for (int t = 0; t < tree->ntypes; ++t) {
         info->tree_start[t] = m[t].start;
         info->tree_count[t] = m[t].count;
@@ -219,9 +221,9 @@ int qbvh_info(const qbvh_t *tree, qbvh_info_t *info) {
             info->root_hi[t][d] = m[t].hi[d];
         }
         info->h[t] = m[t].h;
-        nslots = m[t].end > nslots ? m[t].end : nslots;
+        nrec = m[t].end > nrec ? m[t].end : nrec;
     }
-    info->nslots = tree->n > 0 ? nslots : 0;
+    info->nrecords = tree->n > 0 ? nrec : 0;
     return QBVH_OK;
 }
 
@@ -243,7 +245,8 @@ int qbvh_export(const qbvh_t *tree, int32_t what, void *d_dst, size_t dst_bytes,
     case QBVH_EXPORT_LEAF_PARENT: src = w.leaf_parent; bytes = n * 4; break;
     case QBVH_EXPORT_BOX_LO: src = w.box_lo; bytes = n * 16; break;
     case QBVH_EXPORT_BOX_HI: src = w.box_hi; bytes = n * 16; break;
-    case QBVH_EXPORT_SLOTS: src = w.slots; bytes = (n > 0 ? 2 * n - 1 : 0) * 16; break;
+    case QBVH_EXPORT_RECORDS: src = w.records; bytes = n * 32; break;
+    case QBVH_EXPORT_ROPES: src = w.ropes; bytes = n * 4; break;
     default: return QBVH_EINVAL;
     }
     if (bytes > dst_bytes) bytes = dst_bytes;

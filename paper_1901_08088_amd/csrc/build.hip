@@ -1,21 +1,24 @@
 // Tree build: Morton codes, Z-order sort, Karras radix tree, bottom-up boxes,
-// quantized rope-linked node layout (Section 2.1 and Section 2.2, Fig. 3).
+// quantized rope-linked records (Section 2.1 and Section 2.2, Fig. 3).
 //
-// Layout written here (16-byte slots, depth-first preorder per type tree):
-//   internal node: w_d = q_lo_d | (q_hi_d << 16) for d = x, y, z; w_3 = rope
-//   particle:      w_0..w_2 = fp32 bits of x, y, z; w_3 = ~original index
-// The left child of an internal node is the next slot and a particle's rope is
-// the next slot, so only the rope of an internal node is stored.  A subtree of
-// at most `leaf_size` particles is stored as that many particle slots.
+// Records (32 bytes, depth-first preorder per type tree), one per internal
+// node whose particle range is longer than `leaf_size`:
+//   words 0-2: quantized box of the left child,  w_d = q_lo_d | (q_hi_d << 16)
+//   words 3-5: quantized box of the right child, same packing
+//   word 6/7:  left/right child: record index (>= 0) or the particle run
+//              ~((first << 3) | (count - 1)) when the child holds at most
+//              `leaf_size` particles
+// plus ropes[v], the record after v's subtree.  The left child's record is
+// the next record.  Storing both child boxes in the parent lets one step of
+// the walk test two boxes, halving the chain of dependent node loads.
 //
-// Slot positions come from one scan instead of a top-down walk.  With C[f] the
-// number of kept internal nodes whose particle range starts at sorted position
-// f and P its exclusive scan:
-//   particle k        -> slot k + P[k + 1]
-//   kept node [f, l]  -> slot f + P[f] + (number of its ancestors that share f)
-//   rope of [f, l]    -> slot (l + 1) + P[l + 1]
-// because in preorder the slots before a node are the particles before f, the
-// kept nodes starting before f, and its ancestors starting at f.
+// Record positions come from one scan instead of a top-down walk.  With C[f]
+// the number of kept nodes whose particle range starts at sorted position f
+// and P its exclusive scan:
+//   kept node [f, l] -> record P[f] + (number of its ancestors that share f)
+//   rope of [f, l]   -> record P[l + 1]
+// because in preorder the records before a node are the kept nodes starting
+// before f and its ancestors starting at f.
 #include "qbvh_internal.h"
 
 namespace qbi {
@@ -44,6 +47,9 @@ __device__ __forceinline__ uint32_t morton_bin(float x, double scale) {
 struct Segment {
     int32_t s, e;
 };
+
+// Particle run [first, first + count), count <= 8, as a negative reference.
+__device__ __forceinline__ int32_t run_ref(int32_t first, int32_t count) { return ~((first << 3) | (count - 1)); }
 
 __device__ __forceinline__ Segment segment_of(uint32_t key, int32_t n, int32_t ntypes,
                                               const uint32_t *__restrict__ type_count) {
@@ -164,52 +170,178 @@ __global__ __launch_bounds__(kBuildThreads) void k_karras(const uint32_t *__rest
     if (la - f + 1 > leaf_size) atomicAdd(&kept[f], 1u);
 }
 
-// Bottom-up boxes: every leaf climbs; at each internal node the first arrival
-// stops and the second merges both children and continues.  The visit
-// counter is an agent-scope acquire-release atomic so the sibling's box,
-// written before its own arrival, is visible to the merging thread.
-__global__ __launch_bounds__(kBuildThreads) void k_fit(const float4 *__restrict__ sorted,
-                                                       const int32_t *__restrict__ left,
-                                                       const int32_t *__restrict__ right,
-                                                       const int32_t *__restrict__ parent,
-                                                       const int32_t *__restrict__ leaf_parent, uint32_t *visit,
-                                                       float4 *box_lo, float4 *box_hi, int32_t n) {
-    const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
-    if (k >= n) return;
-    int32_t p = leaf_parent[k];
-    // Each level of the radix tree consumes at least one bit of the 64-bit
-    // augmented key, so no climb is longer than 65 steps; the bound only
-    // guarantees termination.
-    for (int step = 0; p >= 0 && step < kMaxDepth; ++step) {
-        const uint32_t old = __hip_atomic_fetch_add(&visit[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0) return;
-        const int32_t c0 = left[p], c1 = right[p];
-        float4 alo, ahi, blo, bhi;
-        if (c0 < 0) {
-            alo = sorted[~c0];
-            ahi = alo;
-        } else {
-            alo = box_lo[c0];
-            ahi = box_hi[c0];
+// Bottom-up boxes (Section 2.1: boxes are fit by walking up the tree from the
+// leaves).  Every leaf climbs; at each internal node an atomic visit counter
+// lets the first arrival stop and the second merge both children and go on.
+//
+// The counters are synchronized within one workgroup only: an agent-scope
+// acquire/release on gfx950 writes back and invalidates the XCD's L2 at every
+// step, which is far too slow for N atomic steps.  So the climb is split by
+// sorted position into chunks.  A node whose particle range lies inside one
+// chunk has both children inside it, so only that chunk's workgroup ever
+// touches its counter.  Level 0 uses chunks of kFitChunk positions with
+// counters and boxes in LDS; every further level multiplies the chunk by
+// kFitFanout and climbs in global memory with workgroup-scope atomics,
+// starting from the nodes the previous level left at its chunk borders (the
+// "frontier": finished nodes whose parent straddles a border).  The last
+// level has one chunk and reaches every root.  A frontier holds at most two
+// border chains of the tree (each at most 65 deep), so kFrontierCap suffices.
+constexpr int kFitChunk = 2048;
+constexpr int kFitThreads = 1024;
+constexpr int kFitFanout = 256;
+constexpr int kFrontierCap = 160;
+
+__device__ __forceinline__ void frontier_push(int32_t c, uint32_t *s_fcount, int32_t *s_front, int32_t *err) {
+    const uint32_t slot = atomicAdd(s_fcount, 1u);
+    if (slot < (uint32_t)kFrontierCap)
+        s_front[slot] = c;
+    else
+        atomicOr(err, 2);
+}
+
+__global__ __launch_bounds__(kFitThreads) void k_fit_local(const float4 *__restrict__ sorted,
+                                                           const int32_t *__restrict__ left,
+                                                           const int32_t *__restrict__ right,
+                                                           const int32_t *__restrict__ rf,
+                                                           const int32_t *__restrict__ rl,
+                                                           const int32_t *__restrict__ parent,
+                                                           const int32_t *__restrict__ leaf_parent, int32_t n,
+                                                           float4 *__restrict__ box_lo, float4 *__restrict__ box_hi,
+                                                           int32_t *__restrict__ front, uint32_t *__restrict__ fcount,
+                                                           int32_t *err) {
+    __shared__ float s_box[6][kFitChunk];
+    __shared__ uint32_t s_visit[kFitChunk];
+    __shared__ int32_t s_front[kFrontierCap];
+    __shared__ uint32_t s_fcount;
+    const int32_t c0 = blockIdx.x * kFitChunk;
+    const int32_t c1 = min(c0 + kFitChunk, n);
+    for (int i = threadIdx.x; i < kFitChunk; i += kFitThreads) s_visit[i] = 0;
+    if (threadIdx.x == 0) s_fcount = 0;
+    __syncthreads();
+    for (int32_t k = c0 + threadIdx.x; k < c1; k += kFitThreads) {
+        int32_t c = ~k;
+        int32_t p = leaf_parent[k];
+        for (int step = 0; p >= 0 && step < kMaxDepth; ++step) {
+            if (rf[p] < c0 || rl[p] >= c0 + kFitChunk) {
+                frontier_push(c, &s_fcount, s_front, err);
+                break;
+            }
+            const uint32_t old = __hip_atomic_fetch_add(&s_visit[p - c0], 1u, __ATOMIC_ACQ_REL,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0) break;
+            float lo[3], hi[3];
+            const int32_t ch[2] = {left[p], right[p]};
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                float clo[3], chi[3];
+                if (ch[side] < 0) {
+                    const float4 q = sorted[~ch[side]];
+                    clo[0] = chi[0] = q.x;
+                    clo[1] = chi[1] = q.y;
+                    clo[2] = chi[2] = q.z;
+                } else {
+                    const int32_t j = ch[side] - c0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        clo[d] = s_box[d][j];
+                        chi[d] = s_box[3 + d][j];
+                    }
+                }
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    lo[d] = side ? fminf(lo[d], clo[d]) : clo[d];
+                    hi[d] = side ? fmaxf(hi[d], chi[d]) : chi[d];
+                }
+            }
+            const int32_t j = p - c0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                s_box[d][j] = lo[d];
+                s_box[3 + d][j] = hi[d];
+            }
+            c = p;
+            p = parent[p];
         }
-        if (c1 < 0) {
-            blo = sorted[~c1];
-            bhi = blo;
-        } else {
-            blo = box_lo[c1];
-            bhi = box_hi[c1];
-        }
-        box_lo[p] = make_float4(fminf(alo.x, blo.x), fminf(alo.y, blo.y), fminf(alo.z, blo.z), 0.0f);
-        box_hi[p] = make_float4(fmaxf(ahi.x, bhi.x), fmaxf(ahi.y, bhi.y), fmaxf(ahi.z, bhi.z), 0.0f);
-        p = parent[p];
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kFitChunk; i += kFitThreads) {
+        if (s_visit[i] == 2) {
+            box_lo[c0 + i] = make_float4(s_box[0][i], s_box[1][i], s_box[2][i], 0.0f);
+            box_hi[c0 + i] = make_float4(s_box[3][i], s_box[4][i], s_box[5][i], 0.0f);
+        }
+    }
+    const uint32_t fc = min(s_fcount, (uint32_t)kFrontierCap);
+    for (uint32_t i = threadIdx.x; i < fc; i += kFitThreads) front[(int64_t)blockIdx.x * kFrontierCap + i] = s_front[i];
+    if (threadIdx.x == 0) fcount[blockIdx.x] = fc;
+}
+
+// One level above the first: chunks of `chunk` positions, starting from the
+// frontiers of the `fan` previous-level chunks each contains.
+__global__ __launch_bounds__(kFitThreads) void k_fit_level(const float4 *__restrict__ sorted,
+                                                           const int32_t *__restrict__ left,
+                                                           const int32_t *__restrict__ right,
+                                                           const int32_t *__restrict__ rf,
+                                                           const int32_t *__restrict__ rl,
+                                                           const int32_t *__restrict__ parent,
+                                                           const int32_t *__restrict__ leaf_parent, int64_t chunk,
+                                                           int32_t nprev, const int32_t *__restrict__ front_in,
+                                                           const uint32_t *__restrict__ fcount_in, uint32_t *visit,
+                                                           float4 *box_lo, float4 *box_hi,
+                                                           int32_t *__restrict__ front_out,
+                                                           uint32_t *__restrict__ fcount_out, int32_t *err) {
+    __shared__ int32_t s_front[kFrontierCap];
+    __shared__ uint32_t s_fcount;
+    const int64_t c0 = (int64_t)blockIdx.x * chunk;
+    const int64_t c1 = c0 + chunk;
+    if (threadIdx.x == 0) s_fcount = 0;
+    __syncthreads();
+    const int32_t j0 = blockIdx.x * kFitFanout;
+    for (int idx = threadIdx.x; idx < kFitFanout * kFrontierCap; idx += kFitThreads) {
+        const int32_t jc = j0 + idx / kFrontierCap;
+        const uint32_t slot = (uint32_t)(idx % kFrontierCap);
+        if (jc >= nprev || slot >= fcount_in[jc]) continue;
+        int32_t c = front_in[(int64_t)jc * kFrontierCap + slot];
+        int32_t p = c < 0 ? leaf_parent[~c] : parent[c];
+        for (int step = 0; p >= 0 && step < kMaxDepth; ++step) {
+            if (rf[p] < c0 || rl[p] >= c1) {
+                frontier_push(c, &s_fcount, s_front, err);
+                break;
+            }
+            const uint32_t old = __hip_atomic_fetch_add(&visit[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0) break;
+            const int32_t c0i = left[p], c1i = right[p];
+            float4 alo, ahi, blo, bhi;
+            if (c0i < 0) {
+                alo = sorted[~c0i];
+                ahi = alo;
+            } else {
+                alo = box_lo[c0i];
+                ahi = box_hi[c0i];
+            }
+            if (c1i < 0) {
+                blo = sorted[~c1i];
+                bhi = blo;
+            } else {
+                blo = box_lo[c1i];
+                bhi = box_hi[c1i];
+            }
+            box_lo[p] = make_float4(fminf(alo.x, blo.x), fminf(alo.y, blo.y), fminf(alo.z, blo.z), 0.0f);
+            box_hi[p] = make_float4(fmaxf(ahi.x, bhi.x), fmaxf(ahi.y, bhi.y), fmaxf(ahi.z, bhi.z), 0.0f);
+            c = p;
+            p = parent[p];
+        }
+    }
+    __syncthreads();
+    const uint32_t fc = min(s_fcount, (uint32_t)kFrontierCap);
+    for (uint32_t i = threadIdx.x; i < fc; i += kFitThreads) front_out[(int64_t)blockIdx.x * kFrontierCap + i] = s_front[i];
+    if (threadIdx.x == 0) fcount_out[blockIdx.x] = fc;
 }
 
 // Root box, grid spacing and slot range of each type's tree.
 __global__ void k_meta(int32_t n, int32_t ntypes, const uint32_t *__restrict__ type_count,
                        const float4 *__restrict__ sorted, const float4 *__restrict__ box_lo,
                        const float4 *__restrict__ box_hi, const uint32_t *__restrict__ P, int32_t qbits,
-                       double ext_floor, TreeMeta *__restrict__ meta) {
+                       int32_t leaf_size, double ext_floor, TreeMeta *__restrict__ meta) {
     const int t = threadIdx.x;
     if (t >= ntypes) return;
     int32_t s = 0;
@@ -239,8 +371,8 @@ __global__ void k_meta(int32_t n, int32_t ntypes, const uint32_t *__restrict__ t
     m.inv_h = 1.0 / m.h;
     m.start = s;
     m.count = c;
-    m.root = s + (int32_t)P[s];
-    m.end = (s + c) + (int32_t)P[s + c];
+    m.root = (c > leaf_size) ? (int32_t)P[s] : run_ref(s, c > 0 ? c : 1);
+    m.end = (int32_t)P[s + c];
     m.pad[0] = m.pad[1] = 0;
     meta[t] = m;
 }
@@ -259,50 +391,93 @@ __device__ __forceinline__ uint32_t quantize_hi(float v, float root, double h, u
     return (uint32_t)q;
 }
 
-// Write every slot: particle k always, internal node k when it exists and is kept.
+__device__ __forceinline__ uint32_t quantize_axis(float lo, float hi, float root, double h, uint32_t qmax) {
+    return quantize_lo(lo, root, h, qmax) | (quantize_hi(hi, root, h, qmax) << 16);
+}
+
+// One record per kept internal node (Karras id i).
 __global__ __launch_bounds__(kBuildThreads) void k_emit(int32_t n, int32_t ntypes,
                                                         const uint32_t *__restrict__ keys,
                                                         const uint32_t *__restrict__ type_count,
                                                         const float4 *__restrict__ sorted,
                                                         const int32_t *__restrict__ left,
+                                                        const int32_t *__restrict__ right,
                                                         const int32_t *__restrict__ rf, const int32_t *__restrict__ rl,
                                                         const int32_t *__restrict__ parent,
                                                         const float4 *__restrict__ box_lo,
                                                         const float4 *__restrict__ box_hi,
                                                         const uint32_t *__restrict__ P,
                                                         const TreeMeta *__restrict__ meta, int32_t leaf_size,
-                                                        int32_t qbits, uint4 *__restrict__ slots) {
-    const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
-    if (k >= n) return;
-    const float4 p = sorted[k];
-    slots[k + (int32_t)P[k + 1]] =
-        make_uint4(__float_as_uint(p.x), __float_as_uint(p.y), __float_as_uint(p.z), __float_as_uint(p.w));
-
-    const uint32_t key = keys[k];
+                                                        int32_t qbits, uint4 *__restrict__ records,
+                                                        int32_t *__restrict__ ropes) {
+    const int32_t i = blockIdx.x * kBuildThreads + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t key = keys[i];
     const Segment g = segment_of(key, n, ntypes, type_count);
-    if (k >= g.e - 1) return;  // not an internal node id
-    const int32_t f = rf[k], l = rl[k];
-    if (l - f + 1 <= leaf_size) return;  // collapsed into particle slots
+    if (i >= g.e - 1) return;  // not an internal node id
+    const int32_t f = rf[i], l = rl[i];
+    if (l - f + 1 <= leaf_size) return;  // inside a particle run
     int32_t rank = 0;
-    int32_t u = k;
+    int32_t u = i;
     for (int step = 0; step < kMaxDepth; ++step) {
         const int32_t pp = parent[u];
         if (pp < 0 || left[pp] != u) break;
         ++rank;
         u = pp;
     }
-    const int32_t at = f + (int32_t)P[f] + rank;
-    const int32_t rope = (l + 1) + (int32_t)P[l + 1];
+    const int32_t at = (int32_t)P[f] + rank;
     const TreeMeta &m = meta[ntypes == 1 ? 0 : (key >> 30)];
     const uint32_t qmax = (1u << qbits) - 1u;
-    const float4 lo = box_lo[k], hi = box_hi[k];
-    const uint32_t wx = quantize_lo(lo.x, m.lo[0], m.h, qmax) | (quantize_hi(hi.x, m.lo[0], m.h, qmax) << 16);
-    const uint32_t wy = quantize_lo(lo.y, m.lo[1], m.h, qmax) | (quantize_hi(hi.y, m.lo[1], m.h, qmax) << 16);
-    const uint32_t wz = quantize_lo(lo.z, m.lo[2], m.h, qmax) | (quantize_hi(hi.z, m.lo[2], m.h, qmax) << 16);
-    slots[at] = make_uint4(wx, wy, wz, (uint32_t)rope);
+    uint32_t w[8];
+    const int32_t ch[2] = {left[i], right[i]};
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int32_t c = ch[side];
+        float4 lo, hi;
+        int32_t ref;
+        if (c < 0) {
+            lo = hi = sorted[~c];
+            ref = run_ref(~c, 1);
+        } else {
+            lo = box_lo[c];
+            hi = box_hi[c];
+            const int32_t cf = rf[c], cl = rl[c];
+            if (cl - cf + 1 > leaf_size)
+                ref = side == 0 ? at + 1 : (int32_t)P[cf];
+            else
+                ref = run_ref(cf, cl - cf + 1);
+        }
+        w[3 * side + 0] = quantize_axis(lo.x, hi.x, m.lo[0], m.h, qmax);
+        w[3 * side + 1] = quantize_axis(lo.y, hi.y, m.lo[1], m.h, qmax);
+        w[3 * side + 2] = quantize_axis(lo.z, hi.z, m.lo[2], m.h, qmax);
+        w[6 + side] = (uint32_t)ref;
+    }
+    records[2 * (int64_t)at] = make_uint4(w[0], w[1], w[2], w[3]);
+    records[2 * (int64_t)at + 1] = make_uint4(w[4], w[5], w[6], w[7]);
+    ropes[at] = (int32_t)P[l + 1];
 }
 
 inline dim3 grid_for(int64_t items) { return dim3((unsigned)((items + kBuildThreads - 1) / kBuildThreads)); }
+
+int32_t fit_chunks0(int32_t cap) { return (cap + kFitChunk - 1) / kFitChunk; }
+
+hipError_t launch_fit(const Workspace &w, int32_t n, hipStream_t s) {
+    int32_t nchunks = fit_chunks0(n);
+    hipLaunchKernelGGL(k_fit_local, dim3(nchunks), dim3(kFitThreads), 0, s, w.sorted, w.left, w.right, w.rf, w.rl,
+                       w.parent, w.leaf_parent, n, w.box_lo, w.box_hi, w.front[0], w.fcount[0], w.err);
+    int64_t chunk = kFitChunk;
+    int which = 0;
+    while (chunk < n) {
+        const int32_t nprev = nchunks;
+        chunk *= kFitFanout;
+        nchunks = (int32_t)((n + chunk - 1) / chunk);
+        hipLaunchKernelGGL(k_fit_level, dim3(nchunks), dim3(kFitThreads), 0, s, w.sorted, w.left, w.right, w.rf,
+                           w.rl, w.parent, w.leaf_parent, chunk, nprev, w.front[which], w.fcount[which], w.visit,
+                           w.box_lo, w.box_hi, w.front[which ^ 1], w.fcount[which ^ 1], w.err);
+        which ^= 1;
+    }
+    return hipGetLastError();
+}
 
 }  // namespace
 
@@ -319,8 +494,10 @@ size_t workspace_bytes(int32_t cap) {
     b += al(c * 4);                           // visit
     b += 2 * al(c * 16);                      // boxes
     b += al((c + 1) * 4) + al(sb * 4);        // kept + scan partials
-    b += al(2 * c * 16);                      // slots
+    b += al(c * 32) + al(c * 4);              // records + ropes
     b += al(QBVH_MAX_TYPES * sizeof(TreeMeta)) + al(QBVH_MAX_TYPES * 4) + al(4);
+    const size_t nf = (size_t)fit_chunks0((int32_t)c);
+    b += 2 * (al(nf * kFrontierCap * 4) + al(nf * 4));  // fit frontiers (ping-pong)
     return b;
 }
 
@@ -356,10 +533,16 @@ void workspace_carve(Workspace &w, void *base, int32_t cap) {
     w.box_hi = (float4 *)take(c * 16);
     w.kept = (uint32_t *)take((c + 1) * 4);
     w.scan_part = (uint32_t *)take(sb * 4);
-    w.slots = (uint4 *)take(2 * c * 16);
+    w.records = (uint4 *)take(c * 32);
+    w.ropes = (int32_t *)take(c * 4);
     w.meta = (TreeMeta *)take(QBVH_MAX_TYPES * sizeof(TreeMeta));
     w.type_count = (uint32_t *)take(QBVH_MAX_TYPES * 4);
     w.err = (int32_t *)take(4);
+    const size_t nf = (size_t)fit_chunks0((int32_t)c);
+    for (int i = 0; i < 2; ++i) {
+        w.front[i] = (int32_t *)take(nf * kFrontierCap * 4);
+        w.fcount[i] = (uint32_t *)take(nf * 4);
+    }
     w.bytes = (size_t)(p - (char *)base);
 }
 
@@ -377,19 +560,21 @@ hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d
         hipLaunchKernelGGL(k_gather, grid_for(n), dim3(kBuildThreads), 0, s, d_pos, w.vals, n, w.sorted);
         hipLaunchKernelGGL(k_karras, grid_for(n), dim3(kBuildThreads), 0, s, w.keys, n, ntypes, w.type_count,
                            leaf_size, w.left, w.right, w.rf, w.rl, w.parent, w.leaf_parent, w.visit, w.kept);
-        hipLaunchKernelGGL(k_fit, grid_for(n), dim3(kBuildThreads), 0, s, w.sorted, w.left, w.right, w.parent,
-                           w.leaf_parent, w.visit, w.box_lo, w.box_hi, n);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = launch_fit(w, n, s);
+        if (e != hipSuccess) return e;
     }
     e = launch_exclusive_scan(w.kept, n + 1, w.scan_part, s);
     if (e != hipSuccess) return e;
     const double lmax = (double)fmaxf(box[0], fmaxf(box[1], box[2]));
     const double ext_floor = lmax * 0x1p-24;
     hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, s, n, ntypes, w.type_count, w.sorted, w.box_lo, w.box_hi,
-                       w.kept, qbits, ext_floor, w.meta);
+                       w.kept, qbits, leaf_size, ext_floor, w.meta);
     if (n > 0)
         hipLaunchKernelGGL(k_emit, grid_for(n), dim3(kBuildThreads), 0, s, n, ntypes, w.keys, w.type_count,
-                           w.sorted, w.left, w.rf, w.rl, w.parent, w.box_lo, w.box_hi, w.kept, w.meta, leaf_size,
-                           qbits, w.slots);
+                           w.sorted, w.left, w.right, w.rf, w.rl, w.parent, w.box_lo, w.box_hi, w.kept, w.meta,
+                           leaf_size, qbits, w.records, w.ropes);
     return hipGetLastError();
 }
 

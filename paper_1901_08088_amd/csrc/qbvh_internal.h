@@ -16,8 +16,8 @@ struct TreeMeta {
     double inv_h;     // 1 / h
     int32_t start;    // first sorted position of the type
     int32_t count;    // particles of the type
-    int32_t root;     // slot index of the root
-    int32_t end;      // one past the last slot of this tree
+    int32_t root;     // root record index, or the particle run of a tree of <= leaf_size particles
+    int32_t end;      // one past the last record of this tree
     int32_t pad[2];
 };
 static_assert(sizeof(TreeMeta) == 64, "TreeMeta is 64 bytes");
@@ -38,10 +38,13 @@ struct Workspace {
     float4 *box_lo = nullptr, *box_hi = nullptr;
     uint32_t *kept = nullptr;       // [cap + 1]: kept-node counts, scanned in place
     uint32_t *scan_part = nullptr;  // [scan blocks + 1]
-    uint4 *slots = nullptr;         // [2 * cap]
+    uint4 *records = nullptr;       // [cap][2]: two-wide quantized records
+    int32_t *ropes = nullptr;       // [cap]
     TreeMeta *meta = nullptr;       // [QBVH_MAX_TYPES]
     uint32_t *type_count = nullptr; // [QBVH_MAX_TYPES]
     int32_t *err = nullptr;         // [1]
+    int32_t *front[2] = {nullptr, nullptr};    // bottom-up fit frontiers (ping-pong)
+    uint32_t *fcount[2] = {nullptr, nullptr};
 };
 
 size_t workspace_bytes(int32_t cap);
@@ -49,7 +52,8 @@ void workspace_carve(Workspace &w, void *base, int32_t cap);
 
 // Traversal arguments (passed by value as the kernel argument block).
 struct TravArgs {
-    const uint4 *slots;
+    const uint4 *records;
+    const int32_t *ropes;
     const float4 *sorted;
     const TreeMeta *meta;
     int32_t *nbr;

@@ -44,7 +44,7 @@ def test_workspace_bytes():
     assert 100 < b / 1_000_000 < 200  # about 128 bytes per particle
     assert Q.qbvh_workspace_bytes(-1) == 0
     assert Q.qbvh_workspace_bytes(10, ntypes=5) == 0
-    assert Q.qbvh_workspace_bytes(10, opts={"leaf_size": 40}) == 0
+    assert Q.qbvh_workspace_bytes(10, opts={"leaf_size": 9}) == 0
 
 
 def _build_rc(n=10, ntypes=1, box=(5.0, 5.0, 5.0), opts=None, pos=1, typ=None, tree_ptr=True):
@@ -68,7 +68,7 @@ def _build_rc(n=10, ntypes=1, box=(5.0, 5.0, 5.0), opts=None, pos=1, typ=None, t
     dict(box=(float("inf"), 5.0, 5.0)),
     dict(pos=0),
     dict(ntypes=2, typ=None),
-    dict(opts={"leaf_size": 33}),
+    dict(opts={"leaf_size": 9}),
     dict(opts={"leaf_size": -1}),
     dict(opts={"qbits": 7}),
     dict(opts={"qbits": 17}),

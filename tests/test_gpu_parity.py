@@ -55,14 +55,16 @@ def _step_parity(cfg, leaf_size=1, qbits=16):
             assert np.array_equal(blo[i, :3], lo) and np.array_equal(bhi[i, :3], hi)
         if e - s >= 2:
             assert parent[s] == -1
-    nslots = info["nslots"]
-    assert nslots == ref["slots"].shape[0]
-    slots = export(tree, "slots", nslots, torch.int32, 4).view(np.uint32)
-    mism = np.nonzero(np.any(slots != ref["slots"], axis=1))[0]
-    assert mism.size == 0, f"{mism.size} slot mismatches, first {mism[:5].tolist()}"
+    nrec = info["nrecords"]
+    assert nrec == ref["records"].shape[0]
+    rec = export(tree, "records", nrec, torch.int32, 8).view(np.uint32)
+    ropes = export(tree, "ropes", nrec, torch.int32)
+    mism = np.nonzero(np.any(rec != ref["records"], axis=1))[0]
+    assert mism.size == 0, f"{mism.size} record mismatches, first {mism[:5].tolist()}"
+    assert np.array_equal(ropes, ref["ropes"])
     for t, m in enumerate(ref["meta"]):
-        assert info["tree_root"][t] == m["root"] and info["tree_end"][t] == m["end"]
         if m["count"]:
+            assert info["tree_root"][t] == m["root"] and info["tree_end"][t] == m["end"]
             assert np.array_equal(np.float32(info["root_lo"][t]), m["lo"])
             assert np.array_equal(np.float32(info["root_hi"][t]), m["hi"])
             assert info["h"][t] == m["h"]

@@ -165,13 +165,23 @@ def test_grid_spacing_floor_for_coincident_points():
 
 # --------------------------------------------------- layout: Algorithm 1 on the CPU
 
-def _alg1_rows(slots, meta, box, rlist2, qtypes, qpos, orig_of_query):
-    """The paper's stackless traversal over the emitted layout, in plain Python.
+def _run(ref):
+    """Decode a particle-run reference: (first, count)."""
+    ref = int(ref)
+    v = ~(ref - (1 << 32) if ref >= (1 << 31) else ref)
+    return v >> 3, (v & 7) + 1
 
-    Internal slot: decode the quantized box (root lo + q * h) and test it
-    against the search sphere (nearest point, eq. 2) with a tiny pad; on
-    overlap go to the next slot, else follow the rope.  Particle slot: exact
-    fp64 minimum-image distance as the list definition; then the next slot.
+
+def _alg1_rows(records, ropes, meta, box, rlist2, qtypes, qpos, orig_of_query, sorted_pos, perm,
+               types_sorted):
+    """The paper's stackless traversal over the emitted records, in plain Python.
+
+    At a record both child boxes are decoded (root lo + q * h) and tested
+    against the search sphere with the nearest-point rule (eq. 2, tiny pad).
+    Every particle of a hit particle run is a candidate, decided by the exact
+    fp64 minimum-image distance of the list definition.  The walk goes to the
+    left child's record if that box is hit, else to the right child's record
+    if that box is hit, else along the rope.
     """
     L = np.asarray(box, np.float64)
     rows = []
@@ -192,27 +202,39 @@ def _alg1_rows(slots, meta, box, rlist2, qtypes, qpos, orig_of_query):
                 y = np.minimum(np.maximum(c, rlo), rhi)
                 if np.sum((y - c) ** 2) > r2 * (1 + 1e-12):
                     continue
-                n = m["root"]
-                while n < m["end"]:
-                    w = slots[n]
-                    if int(w[3]) >= 1 << 31:  # particle (negative index encoding)
-                        pj = w[:3].view(np.float32).astype(np.float64)
-                        dx = (pj - x) - shift * L
+
+                def take(first, count):
+                    for k in range(first, first + count):
+                        assert types_sorted[k] == tb
+                        dx = (sorted_pos[k].astype(np.float64) - x) - shift * L
                         d2 = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2]
-                        j = int(np.int64(~np.int64(np.int32(np.uint32(w[3])))))
+                        j = int(perm[k])
                         if d2 <= r2 and j != orig_of_query[qi]:
                             found.append(j)
-                        n += 1
-                    else:
-                        qlo = np.array([int(w[d]) & 0xFFFF for d in range(3)], np.float64)
-                        qhi = np.array([int(w[d]) >> 16 for d in range(3)], np.float64)
-                        lo = rlo + qlo * m["h"]
-                        hi = rlo + qhi * m["h"]
+
+                if m["root"] < 0:
+                    take(*_run(m["root"]))
+                    continue
+                v = m["root"]
+                while v < m["end"]:
+                    w = records[v]
+                    hit = []
+                    for side in range(2):
+                        q = w[3 * side:3 * side + 3]
+                        lo = rlo + np.array([int(a) & 0xFFFF for a in q], np.float64) * m["h"]
+                        hi = rlo + np.array([int(a) >> 16 for a in q], np.float64) * m["h"]
                         y = np.minimum(np.maximum(c, lo), hi)
-                        if np.sqrt(np.sum((y - c) ** 2)) <= R * (1 + 1e-9) + 1e-9:
-                            n += 1
-                        else:
-                            n = int(w[3])
+                        hit.append(np.sqrt(np.sum((y - c) ** 2)) <= R * (1 + 1e-9) + 1e-9)
+                        ref = int(np.int32(np.uint32(w[6 + side])))
+                        if hit[side] and ref < 0:
+                            take(*_run(ref))
+                    left, right = int(np.int32(np.uint32(w[6]))), int(np.int32(np.uint32(w[7])))
+                    if hit[0] and left >= 0:
+                        v = left
+                    elif hit[1] and right >= 0:
+                        v = right
+                    else:
+                        v = int(ropes[v])
         rows.append(sorted(found))
     return rows
 
@@ -223,15 +245,15 @@ def test_layout_traversal_reproduces_brute_force(leaf_size, qbits):
     b = T.build_all(cfg.pos, cfg.box, leaf_size=leaf_size, qbits=qbits)
     r2 = oracle.rlist2_table(cfg.rcut, cfg.skin)
     perm = b["perm"].astype(np.int64)
-    rows = _alg1_rows(b["slots"], b["meta"], cfg.box, r2, np.zeros(cfg.n, np.int64),
-                      b["sorted_pos"], perm)
+    rows = _alg1_rows(b["records"], b["ropes"], b["meta"], cfg.box, r2, np.zeros(cfg.n, np.int64),
+                      b["sorted_pos"], perm, b["sorted_pos"], perm, np.zeros(cfg.n, np.int64))
     rp, cols = oracle.neighbor_lists(cfg.pos, cfg.box, cfg.rcut, cfg.skin, method="brute")
     for k in range(cfg.n):
         i = perm[k]
         assert rows[k] == cols[rp[i]:rp[i + 1]].tolist()
-    # slot count = particles + kept internal nodes (ranges larger than a leaf)
+    # one record per internal node whose particle range is larger than a leaf run
     kept = sum(1 for (f, l) in b["trees"][0] if l - f + 1 > leaf_size)
-    assert b["slots"].shape[0] == cfg.n + kept
+    assert b["records"].shape[0] == kept
 
 
 def test_layout_two_types_and_empty_type():
@@ -242,19 +264,38 @@ def test_layout_two_types_and_empty_type():
     assert b["meta"][1]["count"] == 0
     r2 = oracle.rlist2_table(rcut, 0.25)
     perm = b["perm"].astype(np.int64)
-    rows = _alg1_rows(b["slots"], b["meta"], box, r2, types[perm], b["sorted_pos"], perm)
+    rows = _alg1_rows(b["records"], b["ropes"], b["meta"], box, r2, types[perm], b["sorted_pos"], perm,
+                      b["sorted_pos"], perm, types[perm])
     rp, cols = oracle.neighbor_lists(pos, box, rcut, 0.25, types=types, method="brute")
     for k in range(300):
         i = perm[k]
         assert sorted(rows[k]) == cols[rp[i]:rp[i + 1]].tolist()
 
 
-def test_layout_ropes_point_forward_and_end_at_tree_end():
-    cfg = W.lj_fluid(500, seed=9)
-    b = T.build_all(cfg.pos, cfg.box, leaf_size=2)
-    s = b["slots"]
+def test_layout_tree_smaller_than_a_leaf_run():
+    pos = np.array([[1.0, 1.0, 1.0], [1.5, 1.0, 1.0], [6.0, 6.0, 6.0]], np.float32)
+    b = T.build_all(pos, np.full(3, 9.0, np.float32), leaf_size=4)
     (m,) = b["meta"]
-    internal = s[:, 3] < (1 << 31)
-    idx = np.nonzero(internal)[0]
-    assert np.all(s[idx, 3] > idx) and np.all(s[idx, 3] <= m["end"])
-    assert s[m["root"], 3] == m["end"]  # the root's rope leaves the tree
+    assert b["records"].shape[0] == 0 and _run(m["root"]) == (0, 3)
+
+
+def test_layout_ropes_and_children():
+    cfg = W.lj_fluid(500, seed=9)
+    for leaf_size in (1, 2, 5):
+        b = T.build_all(cfg.pos, cfg.box, leaf_size=leaf_size)
+        rec, ropes = b["records"], b["ropes"]
+        (m,) = b["meta"]
+        idx = np.arange(rec.shape[0])
+        assert np.all(ropes > idx) and np.all(ropes <= m["end"])
+        assert ropes[m["root"]] == m["end"]  # the root's rope leaves the tree
+        left = rec[:, 6].view(np.int32)
+        right = rec[:, 7].view(np.int32)
+        assert np.all((left < 0) | (left == idx + 1))  # an internal left child is the next record
+        # an internal right child follows the left subtree; every run lies in the particle range
+        assert np.all((right < 0) | (right > idx))
+        covered = np.zeros(cfg.n, np.int64)
+        for ref in np.concatenate([left[left < 0], right[right < 0]]):
+            f, c = _run(ref)
+            assert 1 <= c <= leaf_size
+            covered[f:f + c] += 1
+        assert np.all(covered == 1)  # runs partition the particles
