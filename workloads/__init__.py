@@ -143,92 +143,81 @@ def lj_fluid(n_particles: int, seed=None, rho: float = 0.85, rc: float = 3.0,
                   meta={"rho": rho, "seed": seed})
 
 
-def _rsa_insert(rng, box64, n_target, diam_new, existing, cross_min, self_min,
-                batch=65536, max_rounds=100000):
-    """Random sequential addition with a cell grid.
+class _CellGrid:
+    """Points binned into cells of edge >= ``cell`` in a periodic box (sorted by cell)."""
 
-    ``existing`` is a list of (positions [M,3], min distance to a new particle).
-    New particles must be at least ``self_min`` apart from each other.  Trial
-    points are drawn in batches; conflicts within a batch are resolved in draw
-    order so the result is the same as one-at-a-time insertion order.
-    """
-    del diam_new
-    placed = np.empty((0, 3), dtype=np.float64)
-    cell = max([self_min] + [d for _, d in existing])
-    ncell = np.maximum((box64 // cell).astype(np.int64), 1)
-    width = box64 / ncell
+    def __init__(self, pts, box64, cell):
+        self.box = box64
+        self.nc = np.maximum((box64 // cell).astype(np.int64), 1)
+        self.width = box64 / self.nc
+        self.pts = pts
+        c = self.cells(pts)
+        self.order = np.argsort(c, kind="stable")
+        self.starts = np.searchsorted(c[self.order], np.arange(int(self.nc.prod()) + 1))
 
-    def build_grid(pts):
-        c = np.minimum((pts // width).astype(np.int64), ncell - 1)
-        lin = (c[:, 0] * ncell[1] + c[:, 1]) * ncell[2] + c[:, 2]
-        order = np.argsort(lin, kind="stable")
-        starts = np.searchsorted(lin[order], np.arange(ncell.prod() + 1))
-        return order, starts
+    def cells(self, x):
+        c = np.minimum((x // self.width).astype(np.int64), self.nc - 1)
+        return (c[:, 0] * self.nc[1] + c[:, 1]) * self.nc[2] + c[:, 2]
 
-    grids = [(p, d, *build_grid(p)) for p, d in existing]
-    offsets = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+    def clashes(self, trial, dmin, trial_index=None):
+        """True where a trial point lies closer than dmin to a grid point.
 
-    def conflicts(trial, pts, dmin, order, starts):
-        if pts.shape[0] == 0:
-            return np.zeros(trial.shape[0], dtype=bool)
-        c = np.minimum((trial // width).astype(np.int64), ncell - 1)
+        With ``trial_index`` (the grid holds the trials themselves), only grid
+        points with a smaller index count.
+        """
         bad = np.zeros(trial.shape[0], dtype=bool)
-        for off in offsets:
-            cc = np.mod(c + off, ncell)
-            lin = (cc[:, 0] * ncell[1] + cc[:, 1]) * ncell[2] + cc[:, 2]
-            lo = starts[lin]
-            hi = starts[lin + 1]
+        if self.pts.shape[0] == 0 or trial.shape[0] == 0:
+            return bad
+        c = np.minimum((trial // self.width).astype(np.int64), self.nc - 1)
+        for off in _OFFSETS:
+            cc = np.mod(c + off, self.nc)
+            lin = (cc[:, 0] * self.nc[1] + cc[:, 1]) * self.nc[2] + cc[:, 2]
+            lo, hi = self.starts[lin], self.starts[lin + 1]
             cnt = hi - lo
-            maxc = int(cnt.max()) if cnt.size else 0
-            for s in range(maxc):
-                has = cnt > s
-                if not has.any():
-                    break
-                idx = order[lo[has] + s]
-                d = pts[idx] - trial[has]
-                d -= box64 * np.round(d / box64)
-                r2 = np.einsum("ij,ij->i", d, d)
-                bad[np.nonzero(has)[0][r2 < dmin * dmin]] = True
+            for slot in range(int(cnt.max()) if cnt.size else 0):
+                has = np.nonzero(cnt > slot)[0]
+                j = self.order[lo[has] + slot]
+                d = self.pts[j] - trial[has]
+                d -= self.box * np.round(d / self.box)
+                close = np.einsum("ij,ij->i", d, d) < dmin * dmin
+                if trial_index is not None:
+                    close &= j < trial_index[has]
+                bad[has[close]] = True
         return bad
 
+
+_OFFSETS = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+
+
+def _rsa_insert(rng, box64, n_target, existing, self_min, batch=131072, max_rounds=20000):
+    """Random sequential addition: uniform trial points, each kept unless it comes
+    closer than ``self_min`` to a kept point of this species, or closer than the
+    given distance to a point of an ``existing`` species ((points, min distance)).
+
+    Trials are drawn in seeded batches; inside a batch a trial is also dropped
+    when it clashes with an earlier trial of the same batch, so the outcome is
+    a deterministic function of the seed.
+    """
+    placed = np.empty((0, 3), dtype=np.float64)
+    grids = [(_CellGrid(p, box64, d), d) for p, d in existing]
     rounds = 0
     while placed.shape[0] < n_target:
         rounds += 1
         if rounds > max_rounds:
             raise RuntimeError("random sequential addition did not converge")
-        trial = rng.uniform(0.0, 1.0, size=(batch, 3)) * box64
-        ok = np.ones(batch, dtype=bool)
-        for pts, dmin, order, starts in grids:
-            ok &= ~conflicts(trial, pts, dmin, order, starts)
+        m = int(min(batch, max(1024, 8 * (n_target - placed.shape[0]))))
+        trial = rng.uniform(0.0, 1.0, size=(m, 3)) * box64
+        ok = np.ones(m, dtype=bool)
+        for g, d in grids:
+            ok &= ~g.clashes(trial, d)
         if placed.shape[0]:
-            po, ps = build_grid(placed)
-            ok &= ~conflicts(trial, placed, self_min, po, ps)
-        trial = trial[ok]
-        if trial.shape[0] == 0:
-            continue
-        # resolve conflicts inside the batch in draw order (greedy, sequential semantics)
-        keep = []
-        tgrid = {}
-        for t_i, p in enumerate(trial):
-            cidx = tuple(np.minimum((p // width).astype(np.int64), ncell - 1))
-            clash = False
-            for off in offsets:
-                key = tuple(np.mod(np.array(cidx) + off, ncell))
-                for q in tgrid.get(key, ()):
-                    d = trial[q] - p
-                    d -= box64 * np.round(d / box64)
-                    if d @ d < self_min * self_min:
-                        clash = True
-                        break
-                if clash:
-                    break
-            if not clash:
-                keep.append(t_i)
-                tgrid.setdefault(cidx, []).append(t_i)
-                if placed.shape[0] + len(keep) >= n_target:
-                    break
-        placed = np.concatenate([placed, trial[keep]], axis=0)
-    return placed[:n_target]
+            ok &= ~_CellGrid(placed, box64, self_min).clashes(trial, self_min)
+        idx = np.nonzero(ok)[0]
+        cand = trial[idx]
+        own = _CellGrid(cand, box64, self_min)
+        keep = ~own.clashes(cand, self_min, trial_index=np.arange(cand.shape[0]))
+        placed = np.concatenate([placed, cand[keep][: n_target - placed.shape[0]]], axis=0)
+    return placed
 
 
 def colloid_solvent(n_total: int = 1_000_000, seed=SEEDS["colloid"], frac_colloid: float = 0.02,
@@ -252,8 +241,8 @@ def colloid_solvent(n_total: int = 1_000_000, seed=SEEDS["colloid"], frac_colloi
     L = volume ** (1.0 / 3.0)
     box32 = np.full(3, L, dtype=np.float32)
     box64 = box32.astype(np.float64)
-    col = _rsa_insert(rng, box64, n_c, d_colloid, [], 0.0, d_colloid)
-    sol = _rsa_insert(rng, box64, n_s, 1.0, [(col, r_excl)], r_excl, 1.0)
+    col = _rsa_insert(rng, box64, n_c, [], d_colloid)
+    sol = _rsa_insert(rng, box64, n_s, [(col, r_excl)], 1.0)
     pos64 = np.concatenate([sol, col], axis=0)
     types = np.concatenate([np.zeros(n_s, np.int32), np.ones(n_c, np.int32)])
     perm = rng.permutation(n_total)
