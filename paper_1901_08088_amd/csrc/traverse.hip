@@ -41,13 +41,25 @@
 namespace qbi {
 namespace {
 
-__device__ __forceinline__ float grid_bound(uint32_t q16) { return __uint_as_float(0x4B000000u | q16); }
+// The bias 0x4B000000 lives in a VGPR (opaque to the compiler) so that a
+// record word held in an SGPR is decoded by one VALU op (v_or_b32 with a
+// 16-bit source select) instead of two scalar ops: the scalar unit, not the
+// vector ALU, is the scarce issue slot of the shared walk.
+__device__ __forceinline__ uint32_t vgpr_bias() {
+    uint32_t v;
+    asm volatile("v_mov_b32 %0, 0x4b000000" : "=v"(v));
+    return v;
+}
+
+__device__ __forceinline__ float lo_bound(uint32_t w, uint32_t bias) { return __uint_as_float(bias | (w & 0xFFFFu)); }
+__device__ __forceinline__ float hi_bound(uint32_t w, uint32_t bias) { return __uint_as_float(bias | (w >> 16)); }
 
 // Squared grid-unit distance from the query (ux, uy, uz) to a packed box.
-__device__ __forceinline__ float box_d2(uint32_t wx, uint32_t wy, uint32_t wz, float ux, float uy, float uz) {
-    const float cx = fminf(fmaxf(ux, grid_bound(wx & 0xFFFFu)), grid_bound(wx >> 16)) - ux;
-    const float cy = fminf(fmaxf(uy, grid_bound(wy & 0xFFFFu)), grid_bound(wy >> 16)) - uy;
-    const float cz = fminf(fmaxf(uz, grid_bound(wz & 0xFFFFu)), grid_bound(wz >> 16)) - uz;
+__device__ __forceinline__ float box_d2(uint32_t wx, uint32_t wy, uint32_t wz, float ux, float uy, float uz,
+                                        uint32_t bias) {
+    const float cx = __builtin_amdgcn_fmed3f(ux, lo_bound(wx, bias), hi_bound(wx, bias)) - ux;
+    const float cy = __builtin_amdgcn_fmed3f(uy, lo_bound(wy, bias), hi_bound(wy, bias)) - uy;
+    const float cz = __builtin_amdgcn_fmed3f(uz, lo_bound(wz, bias), hi_bound(wz, bias)) - uz;
     return __builtin_fmaf(cz, cz, __builtin_fmaf(cy, cy, cx * cx));
 }
 
@@ -85,41 +97,42 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, const Lane &q, i
                                          const float4 *__restrict__ sorted, uint32_t n, int32_t &cnt,
                                          int32_t (*s_out)[kBlock], int32_t *nbr, int32_t max_nbr) {
     const int32_t v = ~ref;
-    const int32_t first = uniform(v >> 3);
-    const int32_t count = uniform((v & 7) + 1);
-    for (int32_t j0 = 0; j0 < count; j0 += 4) {
-        // issue up to four uniform loads before using any; indices past the run
-        // or the array are clamped and their results ignored
+    const uint32_t first = (uint32_t)uniform(v >> 3);
+    const uint32_t count = (uint32_t)uniform((v & 7) + 1);
+    // a well-formed tree never fails this; it keeps a corrupt reference from
+    // reading outside the particle array
+    if (first + count > n) return;
+    const float4 *run = sorted + first;
+    for (uint32_t j0 = 0; j0 < count; j0 += 4) {
+        // up to four uniform loads issued before any use
         float4 p[4];
-        uint32_t kk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[u] = (j0 + u < count) ? run[j0 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            kk[u] = min((uint32_t)(first + j0 + u), n - 1u);
-            p[u] = sorted[kk[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (j0 + u < count && hit) {
-                const float ax = p[u].x - q.qsx, ay = p[u].y - q.qsy, az = p[u].z - q.qsz;
-                const float d2f = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
-                bool in = d2f <= q.r2in;
-                if (!in && d2f <= q.r2out) {
-                    // shell around the cutoff: the definition's fp64 arithmetic
-                    const double sx = (double)(img % 3 - 1) * L[0];
-                    const double sy = (double)((img / 3) % 3 - 1) * L[1];
-                    const double sz = (double)(img / 9 - 1) * L[2];
-                    const double dx = ((double)p[u].x - (double)q.x) - sx;
-                    const double dy = ((double)p[u].y - (double)q.y) - sy;
-                    const double dz = ((double)p[u].z - (double)q.z) - sz;
-                    in = (dx * dx + dy * dy) + dz * dz <= q.r2;
-                }
-                if (in && (int32_t)kk[u] != q.k)
-                    append<kVec4, kBlock>(~__float_as_int(p[u].w), cnt, s_out, nbr, q.orig, max_nbr);
+            if (j0 + u >= count) break;
+            const float ax = p[u].x - q.qsx, ay = p[u].y - q.qsy, az = p[u].z - q.qsz;
+            const float d2f = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
+            bool in = hit && d2f <= q.r2in;
+            const bool amb = hit && !in && d2f <= q.r2out;
+            if (__any(amb) && amb) {
+                // shell around the cutoff: the definition's fp64 arithmetic
+                const double sx = (double)(img % 3 - 1) * L[0];
+                const double sy = (double)((img / 3) % 3 - 1) * L[1];
+                const double sz = (double)(img / 9 - 1) * L[2];
+                const double dx = ((double)p[u].x - (double)q.x) - sx;
+                const double dy = ((double)p[u].y - (double)q.y) - sy;
+                const double dz = ((double)p[u].z - (double)q.z) - sz;
+                in = (dx * dx + dy * dy) + dz * dz <= q.r2;
             }
+            if (in && (int32_t)(first + j0 + u) != q.k)
+                append<kVec4, kBlock>(~__float_as_int(p[u].w), cnt, s_out, nbr, q.orig, max_nbr);
         }
     }
 }
 
+// The read-only arrays come as separate __restrict__ parameters: that lets the
+// compiler fetch wave-uniform records and particles with scalar loads.
 template <bool kVec4, int kBlock>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_traverse(
     TravArgs a, const uint4 *__restrict__ records, const int32_t *__restrict__ ropes,
@@ -145,6 +158,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         if (k >= meta[t].start) ta = t;
 
     int32_t cnt = 0;
+    const uint32_t bias = vgpr_bias();
     for (int tb = 0; tb < a.ntypes; ++tb) {
         const TreeMeta &m = meta[tb];
         if (m.count == 0) continue;
@@ -217,11 +231,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
             }
             int32_t v = root;
             while (v < end) {
-                const uint4 r0 = records[2 * (int64_t)v];
-                const uint4 r1 = records[2 * (int64_t)v + 1];
-                const int32_t rope = ropes[v];
-                const bool hl = box_d2(r0.x, r0.y, r0.z, q.ux, q.uy, q.uz) <= q.r2g;
-                const bool hr = box_d2(r0.w, r1.x, r1.y, q.ux, q.uy, q.uz) <= q.r2g;
+                const uint4 r0 = records[2 * (uint32_t)v];
+                const uint4 r1 = records[2 * (uint32_t)v + 1];
+                const int32_t rope = ropes[(uint32_t)v];
+                const bool hl = box_d2(r0.x, r0.y, r0.z, q.ux, q.uy, q.uz, bias) <= q.r2g;
+                const bool hr = box_d2(r0.w, r1.x, r1.y, q.ux, q.uy, q.uz, bias) <= q.r2g;
                 const bool anyl = __any(hl), anyr = __any(hr);
                 const int32_t cl = (int32_t)r1.z, cr = (int32_t)r1.w;
                 if (cl < 0 && anyl)

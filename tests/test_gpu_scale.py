@@ -13,7 +13,7 @@ from nlist_check import require_gpu
 
 pytestmark = pytest.mark.gpu
 
-BENCH_OPTS = {"leaf_size": 1, "qbits": 16, "block_size": 256}
+from bench import BENCH_OPTS  # the launch configuration bench.py times
 
 
 @pytest.mark.parametrize("n", [1_000_000, 8_000_000])
