@@ -90,6 +90,164 @@ def copy_probe(mib: int) -> None:
     log(f"copy probe: {mib} MiB read + {mib} MiB written per launch, 3 launches")
 
 
+def batched_vs_plain(steps: int) -> dict:
+    """The 256-replica ensemble (N log-uniform in [2000, 200000], density
+    0.3-0.9, rc 2.5-3.0, skin 0.4, max_nbr 256): one nlist_build_many call
+    (autotuned, graph-replayed) against qbvh_build + nlist_build per replica
+    in sequence on the same stream, both timed over ``steps`` passes."""
+    import torch
+    import paper_1901_08088_amd as Q
+    cfgs = W.ensemble()
+    total = sum(c.n for c in cfgs)
+    log(f"ensemble: {len(cfgs)} replicas, {total:,} particles")
+    systems = []
+    for c in cfgs:
+        systems.append(dict(pos=torch.from_numpy(c.pos).cuda(), types=None, ntypes=1, box=c.box, rcut=c.rcut,
+                            skin=c.skin, max_nbr=256,
+                            nbr=torch.empty((c.n, 256), dtype=torch.int32, device="cuda"),
+                            count=torch.empty(c.n, dtype=torch.int32, device="cuda"),
+                            overflow=torch.empty(1, dtype=torch.int32, device="cuda")))
+    stream = torch.cuda.current_stream()
+    trees = [None] * len(cfgs)
+
+    def plain():
+        for k, (c, y) in enumerate(zip(cfgs, systems)):
+            trees[k] = Q.qbvh_build(y["pos"], None, c.box, 1, BENCH_OPTS, tree=trees[k])
+            Q.nlist_build(trees[k], c.rcut, c.skin, 256, y["nbr"], y["count"], y["overflow"])
+
+    def timed(fn):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(steps):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / steps
+
+    for _ in range(3):
+        plain()
+    plain_ms = timed(plain)
+    plain_pairs = int(sum(int(y["count"].sum()) for y in systems))
+    log(f"plain: {plain_ms:.3f} ms per pass over all replicas")
+    calls = 0
+    while not Q.nlist_batch_stats()["tuned"] or calls < 2:
+        Q.nlist_build_many(systems)
+        calls += 1
+        if calls > 200:
+            raise RuntimeError("autotuner did not settle")
+    torch.cuda.synchronize()
+    st = Q.nlist_batch_stats()
+    log(f"autotuner settled after {calls} calls: {st}")
+    batch_ms = timed(lambda: Q.nlist_build_many(systems))
+    batch_pairs = int(sum(int(y["count"].sum()) for y in systems))
+    if batch_pairs != plain_pairs:
+        raise RuntimeError(f"batched pairs {batch_pairs} != plain pairs {plain_pairs}")
+    log(f"batched: {batch_ms:.3f} ms per call")
+    for t in trees:
+        Q.qbvh_free(t)
+    Q.nlist_batch_release()
+    return {"workload": f"256 LJ replicas, sum N = {total:,} (seed 19010885), rc 2.5-3.0 + skin 0.4, max_nbr 256",
+            "systems": len(cfgs), "particles": total, "directed_pairs": batch_pairs,
+            "plain_ms": plain_ms, "batched_ms": batch_ms,
+            "plain_systems_per_s": len(cfgs) * 1e3 / plain_ms,
+            "batched_systems_per_s": len(cfgs) * 1e3 / batch_ms,
+            "batched_pairs_per_s": batch_pairs * 1e3 / batch_ms,
+            "speedup": plain_ms / batch_ms, "plain_opts": BENCH_OPTS,
+            "tuned": {k: st[k] for k in ("leaf_size", "qbits", "block_size", "candidates")},
+            "tuning_calls": calls}
+
+
+def served(seconds: float, load: float = 0.7) -> dict:
+    """The served stream: 64 simulations (16 liquid-vapor slabs in 60 x 60 x 240
+    boxes and 48 LJ fluids, N log-uniform in [1e4, 2e6], rc 3.0 + skin 0.4,
+    max_nbr 256).  Each request is the simulation's previous positions plus a
+    N(0, 0.05) displacement, wrapped, for a simulation drawn uniformly.  First
+    the saturated throughput of the continuous-batching server is measured
+    (a burst of 2 requests per simulation), then Poisson arrivals at ``load``
+    times that rate run for ``seconds``, against the same stream served one
+    request at a time in FIFO order (one stream, batches of one)."""
+    import torch
+    import paper_1901_08088_amd as Q
+    sims = W.served_sims()
+    total = sum(c.n for c in sims)
+    log(f"served stream: {len(sims)} simulations, {total:,} particles")
+    cur = [torch.from_numpy(c.pos).cuda() for c in sims]
+    boxes = [torch.tensor(c.box, device="cuda") for c in sims]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(19010886)
+
+    def move(k):
+        p = cur[k] + 0.05 * torch.randn(cur[k].shape, device="cuda", generator=gen)
+        p = torch.remainder(p, boxes[k])
+        p = torch.where(p >= boxes[k], torch.zeros_like(p), p)
+        cur[k] = p
+        return p
+
+    budget = 96 << 30
+
+    def burst(srv, per_sim):
+        order = [k for _ in range(per_sim) for k in range(len(sims))]
+        t0 = time.perf_counter()
+        ts = []
+        for k in order:
+            p = move(k)
+            torch.cuda.current_stream().synchronize()
+            ts.append(srv.submit(k, p, sims[k].box, sims[k].rcut, sims[k].skin, 256))
+        for t in ts:
+            srv.wait(t)
+        return len(order) / (time.perf_counter() - t0)
+
+    def poisson(srv, rate):
+        rng = np.random.default_rng(11)
+        t0 = time.perf_counter()
+        nxt = t0
+        ts = []
+        while nxt - t0 < seconds:
+            now = time.perf_counter()
+            if nxt > now:
+                time.sleep(max(0.0, nxt - now - 2e-4))
+                while time.perf_counter() < nxt:
+                    pass
+            k = int(rng.integers(len(sims)))
+            p = move(k)
+            torch.cuda.current_stream().synchronize()
+            ts.append(srv.submit(k, p, sims[k].box, sims[k].rcut, sims[k].skin, 256))
+            nxt += rng.exponential(1.0 / rate)
+            if len(ts) % 64 == 0:
+                log(f"  {len(ts)} requests submitted")
+        for t in ts:
+            srv.wait(t)
+        return srv.stats()
+
+    out = {"workload": f"64 simulations (16 slabs 60x60x240 + 48 LJ fluids, N log-uniform 1e4-2e6, "
+                       f"sum N = {total:,}, seed 19010886), rc 3.0 + skin 0.4, max_nbr 256",
+           "seconds": seconds, "load": load}
+    srv = Q.Server(budget, max_inflight=2, max_batch=64)
+    burst(srv, 1)  # warm-up: sessions allocated, batch workspaces sized
+    sat = burst(srv, 2)
+    srv.close()
+    rate = load * sat
+    log(f"saturated: {sat:.1f} requests/s; Poisson arrivals at {rate:.1f}/s for {seconds:g} s")
+    srv = Q.Server(budget, max_inflight=2, max_batch=64)
+    burst(srv, 1)
+    st = poisson(srv, rate)
+    srv.close()
+    log(f"continuous batching: {st}")
+    fifo = Q.Server(budget, max_inflight=1, max_batch=1)
+    burst(fifo, 1)
+    fsat = burst(fifo, 1)
+    fst = poisson(fifo, rate)
+    fifo.close()
+    log(f"one at a time: {fst}")
+    keys = ("p50_ms", "p99_ms", "mean_ms", "requests_per_s", "particles_per_s", "mean_batch", "completed")
+    out.update({"saturated_requests_per_s": sat, "arrival_rate_per_s": rate,
+                "continuous_batching": {k: st[k] for k in keys},
+                "fifo_saturated_requests_per_s": fsat,
+                "fifo_one_at_a_time": {k: fst[k] for k in keys}})
+    return out
+
+
 def cpu_baseline(cfg, sample_rows: int) -> dict:
     """The oracle's cell list timed on this host for a bounded sample of rows."""
     import oracle
@@ -118,6 +276,10 @@ def main(argv=None) -> int:
     ap.add_argument("--block-size", type=int, default=BENCH_OPTS["block_size"])
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="oracle rows timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--batched-steps", type=int, default=20,
+                    help="passes timed for the batched-vs-plain ensemble comparison (0 = skip)")
+    ap.add_argument("--served-seconds", type=float, default=5.0,
+                    help="Poisson-arrival time of the served-stream comparison (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run a plain copy kernel of this size (counter calibration)")
     args = ap.parse_args(argv)
@@ -185,6 +347,19 @@ def main(argv=None) -> int:
     if args.copy_probe_mib > 0:
         copy_probe(args.copy_probe_mib)
 
+    batched = None
+    if args.batched_steps > 0:
+        log("batched vs plain (ensemble)")
+        del nbr
+        torch.cuda.empty_cache()
+        batched = batched_vs_plain(args.batched_steps)
+
+    serve = None
+    if args.served_seconds > 0:
+        log("served stream")
+        torch.cuda.empty_cache()
+        serve = served(args.served_seconds)
+
     base = None
     if args.cpu_sample > 0:
         log("cpu baseline (oracle)")
@@ -216,6 +391,8 @@ def main(argv=None) -> int:
                      "traffic": measured_traffic(args.workload, opts),
                      "algorithmic_bytes": tbytes, "kernel_sources": kernel_source_hash()},
         "cpu_baseline": base,
+        "batched": batched,
+        "served": serve,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -155,19 +155,144 @@ typedef struct {
     int32_t leaf_size;  /* as qbvh_opts_t; 0 = let the autotuner choose */
     int32_t qbits;      /* as qbvh_opts_t; 0 = let the autotuner choose */
     int32_t block_size; /* as qbvh_opts_t; 0 = let the autotuner choose */
-    int32_t use_graph;  /* 1: capture the launch sequence in a hipGraph and replay
-                           it while the batch shape is unchanged (default 1) */
+    int32_t eager;      /* 0 (default): capture the launch sequence of each batch
+                           shape and configuration once in a hipGraph and replay
+                           it; 1: launch the kernels directly on every call */
 } qbvh_batch_opts_t;
 
 /*
- * nlist_build_many -- build and traverse many independent systems in one
- * launch sequence (every build phase covers all systems at once).  Each
- * system's outputs equal those of qbvh_build + nlist_build on that system
- * alone (same sets, same counts).  The library keeps a batch workspace that
- * grows as needed.
+ * nlist_build_many -- build the trees of many independent systems and write
+ * their exact lists in one launch sequence (Section 2.1 to Section 2.3 per
+ * system; the paper builds one system at a time, here every kernel covers
+ * all systems at once).
+ *
+ *   nsys    number of systems (0: no work).
+ *   sys     host array [nsys]; each entry as for qbvh_build + nlist_build
+ *           (d_pos/d_type/n/ntypes/box as qbvh_build, rcut/skin/max_nbr and
+ *           the outputs as nlist_build).  Inputs are trusted (no device
+ *           validation); the sum of n must stay below 2^28.
+ *   opts    NULL or options; a zero field is chosen by the autotuner.
+ *
+ * Each system's outputs equal those of qbvh_build + nlist_build on that
+ * system alone: the same neighbor sets and identical counts (row order may
+ * differ).  The library keeps, per stream and device, a batch context: a
+ * workspace that grows as needed (growing waits for the stream) and, per
+ * batch shape (the list of n and ntypes, and whether all rows take 16-byte
+ * stores), the autotuner state and the captured graphs.  While tuning, the
+ * calls of one shape cycle through the candidate configurations, each timed
+ * twice with events, then the fastest is kept for that shape.  Pointers,
+ * boxes and cutoffs may change between calls of one shape; they live in a
+ * device table uploaded before the launch when it changed.  Calls on one
+ * stream are serialized by the library; overlapping calls on different
+ * streams use different contexts.
  */
 QBVH_API int nlist_build_many(int32_t nsys, const qbvh_system_t *sys, const qbvh_batch_opts_t *opts,
                      qbvh_stream_t stream);
+
+/* Autotuner state of the last batch shape used on a stream. */
+typedef struct {
+    int32_t tuned;           /* 1 once the configuration is frozen */
+    int32_t leaf_size, qbits, block_size;  /* the chosen configuration (first candidate while tuning) */
+    int32_t candidates;      /* configurations in the search */
+    int32_t graphs_captured; /* graphs captured for this shape so far */
+    int64_t calls;           /* calls of this shape */
+    float best_ms;           /* fastest measured call of the chosen configuration (0 if none) */
+} qbvh_batch_stats_t;
+
+QBVH_API int nlist_batch_stats(qbvh_stream_t stream, qbvh_batch_stats_t *out);
+
+/* Free the batch context of a stream on the current device (waits for the
+ * stream first).  Unknown streams are ignored. */
+QBVH_API void nlist_batch_release(qbvh_stream_t stream);
+
+/* ---------------------------------------------------------------- serving */
+
+/*
+ * A server accepts rebuild requests from many concurrent simulations and
+ * serves them with continuous batching: a worker thread keeps up to
+ * `max_inflight` batches on the device (one stream each); whenever a stream
+ * is free it takes every queued request that is admissible right now and
+ * launches them together as one nlist_build_many call, so requests that
+ * arrive while others run are admitted as soon as a stream and memory free
+ * up, and their work overlaps on the device.
+ *
+ * Sessions.  Every sim_id owns a session holding its list, counts and
+ * overflow flag in device memory; they stay resident after the request
+ * completes and are overwritten by the sim's next request.  (The tree is
+ * rebuilt on every request, as the method rebuilds it at every list update,
+ * so it lives only in the batch workspace.)  Requests of one sim run one at a
+ * time, in submission order.
+ *
+ * Admission by footprint.  A request needs its session's buffers
+ * (n * max_nbr * 4 + n * 4 + 4 bytes) plus its share of the batch
+ * workspace (qbvh_workspace_bytes(n)).  A request is admitted when the bytes
+ * of all resident sessions and of the in-flight batches, plus its own, fit in
+ * `budget_bytes`; idle sessions are evicted, least recently used first, to
+ * make room.  A request that could never fit is refused at submission with
+ * QBVH_EAGAIN; otherwise it waits in FIFO order (a request that does not fit
+ * yet does not block smaller ones behind it).
+ */
+typedef struct qbvh_server qbvh_server_t;
+
+typedef struct {
+    size_t budget_bytes;      /* device bytes for sessions plus batch workspaces (> 0) */
+    int32_t max_inflight;     /* batches on the device at once, 1..8 (0: 2) */
+    int32_t max_batch;        /* requests per batch, >= 1 (0: 64) */
+    qbvh_batch_opts_t batch;  /* options of the batched launches; zero fields take
+                                 leaf 8, 16 bits, 256 work-items; graphs are not used
+                                 (every batch has a new composition) */
+} qbvh_server_opts_t;
+
+typedef struct {
+    int32_t sim_id;           /* session key (>= 0) */
+    const float *d_pos;       /* device float [n][3]; read on the server's own streams, so it
+                                 must already hold its values when submitted (the work that
+                                 wrote it has completed) and stay valid until the request
+                                 completes */
+    const int32_t *d_type;    /* device int32 [n] or NULL when ntypes == 1 (same lifetime) */
+    int32_t n, ntypes;
+    float box[3];
+    const float *rcut;        /* host float [ntypes][ntypes]; copied at submission */
+    float skin;
+    int32_t max_nbr;          /* >= 1 */
+} qbvh_request_t;
+
+typedef struct {
+    int64_t submitted, completed, batches, refused;
+    double p50_ms, p99_ms, mean_ms;  /* latency: submission to completion seen by the worker */
+    double requests_per_s;           /* completed requests / (last completion - first submission) */
+    double particles_per_s;          /* particles of completed requests over the same span */
+    double mean_batch;               /* requests per batch */
+    size_t bytes_resident;           /* session buffers held now */
+    size_t bytes_peak;               /* peak of sessions + in-flight workspaces */
+} qbvh_server_stats_t;
+
+/* Create a server on the current device.  Returns QBVH_EINVAL for bad options. */
+QBVH_API int qbvh_server_create(qbvh_server_t **srv, const qbvh_server_opts_t *opts);
+
+/* Queue a request; *ticket receives its id (> 0).  Arguments are checked as
+ * for qbvh_build + nlist_build (QBVH_EINVAL / QBVH_EGEOM); QBVH_EAGAIN if the
+ * request can never fit the budget.  Never blocks on the device. */
+QBVH_API int qbvh_server_submit(qbvh_server_t *srv, const qbvh_request_t *req, int64_t *ticket);
+
+/* *done = 1 once the request's results are on the device (its stream has
+ * passed them), else 0.  A failed request reports its error code. */
+QBVH_API int qbvh_server_poll(qbvh_server_t *srv, int64_t ticket, int32_t *done);
+
+/* Block until the request completes; returns its status. */
+QBVH_API int qbvh_server_wait(qbvh_server_t *srv, int64_t ticket);
+
+/* Device buffers of a sim's session: d_nbr [n][max_nbr], d_count [n],
+ * d_overflow [1], as nlist_build writes them, for its last completed
+ * request.  Valid until that sim's next request completes or the session is
+ * evicted.  QBVH_EINVAL for an unknown sim or one with nothing completed. */
+QBVH_API int qbvh_server_result(qbvh_server_t *srv, int32_t sim_id, const int32_t **d_nbr, const int32_t **d_count,
+                       const int32_t **d_overflow, int32_t *n, int32_t *max_nbr);
+
+QBVH_API int qbvh_server_stats(qbvh_server_t *srv, qbvh_server_stats_t *stats);
+
+/* Finish every queued and running request, then free the server. */
+QBVH_API void qbvh_server_destroy(qbvh_server_t *srv);
 
 /* Release a handle (waits for its pending work).  NULL is ignored. */
 QBVH_API void qbvh_free(qbvh_t *tree);

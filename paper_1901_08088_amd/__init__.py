@@ -5,10 +5,10 @@ declared in ``include/qbvh.h`` (``libqbvh.so``, built in-tree by
 ``build_ext.py``).  ``capi`` is a thin ctypes binding with the same names.
 The library is loaded on first use, not at import.
 """
-from .capi import (EXPORT, QbvhError, QbvhOpts, Tree, lib, nlist_build, nlist_build_many,  # noqa: F401
-                   qbvh_build, qbvh_export, qbvh_free, qbvh_info, qbvh_strerror,
-                   qbvh_workspace_bytes)
+from .capi import (EXPORT, QbvhError, QbvhOpts, Server, Tree, lib, nlist_batch_release,  # noqa: F401
+                   nlist_batch_stats, nlist_build, nlist_build_many, qbvh_build, qbvh_export, qbvh_free,
+                   qbvh_info, qbvh_strerror, qbvh_workspace_bytes)
 
-__all__ = ["EXPORT", "QbvhError", "QbvhOpts", "Tree", "lib", "nlist_build", "nlist_build_many",
-           "qbvh_build", "qbvh_export", "qbvh_free", "qbvh_info", "qbvh_strerror",
-           "qbvh_workspace_bytes"]
+__all__ = ["EXPORT", "QbvhError", "QbvhOpts", "Server", "Tree", "lib", "nlist_batch_release", "nlist_batch_stats",
+           "nlist_build", "nlist_build_many", "qbvh_build", "qbvh_export", "qbvh_free", "qbvh_info",
+           "qbvh_strerror", "qbvh_workspace_bytes"]

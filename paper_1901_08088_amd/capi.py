@@ -22,8 +22,11 @@ OK, EINVAL, EGEOM, ENOMEM, EHIP, EAGAIN, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 EXPORT = dict(keys=1, perm=2, sorted=3, left=4, right=5, range_f=6, range_l=7, parent=8,
               leaf_parent=9, box_lo=10, box_hi=11, records=12, ropes=13)
 
-C_API = ("qbvh_build", "nlist_build", "nlist_build_many", "qbvh_free", "qbvh_strerror",
-         "qbvh_last_hip_error", "qbvh_workspace_bytes", "qbvh_info", "qbvh_export")
+C_API = ("qbvh_build", "nlist_build", "nlist_build_many", "nlist_batch_stats", "nlist_batch_release",
+         "qbvh_server_create", "qbvh_server_submit", "qbvh_server_poll", "qbvh_server_wait",
+         "qbvh_server_result", "qbvh_server_stats", "qbvh_server_destroy",
+         "qbvh_free", "qbvh_strerror", "qbvh_last_hip_error", "qbvh_workspace_bytes", "qbvh_info",
+         "qbvh_export")
 
 
 class QbvhError(RuntimeError):
@@ -42,7 +45,32 @@ class QbvhOpts(ctypes.Structure):
 
 class QbvhBatchOpts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("qbits", ctypes.c_int32),
-                ("block_size", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("block_size", ctypes.c_int32), ("eager", ctypes.c_int32)]
+
+
+class QbvhBatchStats(ctypes.Structure):
+    _fields_ = [("tuned", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("qbits", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("graphs_captured", ctypes.c_int32), ("calls", ctypes.c_int64), ("best_ms", ctypes.c_float)]
+
+
+class QbvhServerOpts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("batch", QbvhBatchOpts)]
+
+
+class QbvhRequest(ctypes.Structure):
+    _fields_ = [("sim_id", ctypes.c_int32), ("d_pos", ctypes.c_void_p), ("d_type", ctypes.c_void_p),
+                ("n", ctypes.c_int32), ("ntypes", ctypes.c_int32), ("box", ctypes.c_float * 3),
+                ("rcut", ctypes.c_void_p), ("skin", ctypes.c_float), ("max_nbr", ctypes.c_int32)]
+
+
+class QbvhServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("refused", ctypes.c_int64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("requests_per_s", ctypes.c_double),
+                ("particles_per_s", ctypes.c_double), ("mean_batch", ctypes.c_double),
+                ("bytes_resident", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t)]
 
 
 class QbvhSystem(ctypes.Structure):
@@ -82,6 +110,25 @@ def lib():
             L.nlist_build.restype = ctypes.c_int
             L.nlist_build_many.argtypes = [I32, ctypes.POINTER(QbvhSystem), ctypes.POINTER(QbvhBatchOpts), P]
             L.nlist_build_many.restype = ctypes.c_int
+            L.nlist_batch_stats.argtypes = [P, ctypes.POINTER(QbvhBatchStats)]
+            L.nlist_batch_stats.restype = ctypes.c_int
+            L.nlist_batch_release.argtypes = [P]
+            L.nlist_batch_release.restype = None
+            L.qbvh_server_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(QbvhServerOpts)]
+            L.qbvh_server_create.restype = ctypes.c_int
+            L.qbvh_server_submit.argtypes = [P, ctypes.POINTER(QbvhRequest), ctypes.POINTER(ctypes.c_int64)]
+            L.qbvh_server_submit.restype = ctypes.c_int
+            L.qbvh_server_poll.argtypes = [P, ctypes.c_int64, ctypes.POINTER(I32)]
+            L.qbvh_server_poll.restype = ctypes.c_int
+            L.qbvh_server_wait.argtypes = [P, ctypes.c_int64]
+            L.qbvh_server_wait.restype = ctypes.c_int
+            L.qbvh_server_result.argtypes = [P, I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                             ctypes.POINTER(I32), ctypes.POINTER(I32)]
+            L.qbvh_server_result.restype = ctypes.c_int
+            L.qbvh_server_stats.argtypes = [P, ctypes.POINTER(QbvhServerStats)]
+            L.qbvh_server_stats.restype = ctypes.c_int
+            L.qbvh_server_destroy.argtypes = [P]
+            L.qbvh_server_destroy.restype = None
             L.qbvh_free.argtypes = [P]
             L.qbvh_free.restype = None
             L.qbvh_strerror.argtypes = [ctypes.c_int]
@@ -218,6 +265,107 @@ def nlist_build_many(systems, opts=None, stream=None) -> None:
                                  _stream(stream))
     del keep
     _check(rc_, "nlist_build_many")
+
+
+def nlist_batch_stats(stream=None) -> dict:
+    """Autotuner state of the last batch shape used on ``stream``."""
+    st = QbvhBatchStats()
+    _check(lib().nlist_batch_stats(_stream(stream), ctypes.byref(st)), "nlist_batch_stats")
+    return {k: getattr(st, k) for k, _ in QbvhBatchStats._fields_}
+
+
+def nlist_batch_release(stream=None) -> None:
+    """Free the batch context of ``stream`` (waits for the stream)."""
+    lib().nlist_batch_release(_stream(stream))
+
+
+class _DeviceArray:
+    """A device buffer of the library seen through ``__cuda_array_interface__``
+    (torch wraps it without copying)."""
+
+    def __init__(self, ptr: int, shape, typestr: str = "<i4"):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, True),
+                                         "version": 3, "strides": None}
+
+
+class Server:
+    """qbvh_server_*: continuous-batching neighbor-list server (see include/qbvh.h)."""
+
+    def __init__(self, budget_bytes: int, max_inflight: int = 2, max_batch: int = 64, batch_opts=None):
+        o = QbvhServerOpts()
+        o.budget_bytes = int(budget_bytes)
+        o.max_inflight = int(max_inflight)
+        o.max_batch = int(max_batch)
+        if batch_opts:
+            o.batch = QbvhBatchOpts(**{k: int(v) for k, v in dict(batch_opts).items()})
+        h = ctypes.c_void_p(None)
+        _check(lib().qbvh_server_create(ctypes.byref(h), ctypes.byref(o)), "qbvh_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, sim_id: int, pos, box, rcut, skin: float, max_nbr: int, types=None, ntypes: int = 1) -> int:
+        """Queue a rebuild of sim ``sim_id`` from device positions ``pos`` [n, 3] (kept alive
+        until the request completes); returns the ticket."""
+        import torch
+        r = QbvhRequest()
+        r.sim_id = int(sim_id)
+        r.d_pos = _dev_ptr(pos, torch.float32, "pos")
+        r.d_type = _dev_ptr(types, torch.int32, "types", allow_none=True)
+        r.n = int(pos.shape[0])
+        r.ntypes = int(ntypes)
+        for d, v in enumerate(np.asarray(box, dtype=np.float32).reshape(3)):
+            r.box[d] = float(v)
+        rc, rp = _rcut_array(rcut, ntypes)
+        r.rcut = ctypes.cast(rp, ctypes.c_void_p)
+        r.skin = float(skin)
+        r.max_nbr = int(max_nbr)
+        t = ctypes.c_int64(0)
+        _check(lib().qbvh_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)), "qbvh_server_submit")
+        self._keep[t.value] = (pos, types)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int32(0)
+        _check(lib().qbvh_server_poll(self._h, int(ticket), ctypes.byref(done)), "qbvh_server_poll")
+        if done.value:
+            self._keep.pop(ticket, None)
+        return bool(done.value)
+
+    def wait(self, ticket: int) -> None:
+        rc = lib().qbvh_server_wait(self._h, int(ticket))
+        self._keep.pop(ticket, None)
+        _check(rc, "qbvh_server_wait")
+
+    def result(self, sim_id: int):
+        """(nbr [n, max_nbr], count [n], overflow [1]) device tensors viewing the session's buffers."""
+        import torch
+        P = ctypes.c_void_p
+        a, b, c = P(None), P(None), P(None)
+        n, m = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().qbvh_server_result(self._h, int(sim_id), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                        ctypes.byref(n), ctypes.byref(m)), "qbvh_server_result")
+        dev = torch.device("cuda", torch.cuda.current_device())
+        nbr = torch.as_tensor(_DeviceArray(a.value, (n.value, m.value)), device=dev)
+        cnt = torch.as_tensor(_DeviceArray(b.value, (n.value,)), device=dev)
+        ovf = torch.as_tensor(_DeviceArray(c.value, (1,)), device=dev)
+        return nbr, cnt, ovf
+
+    def stats(self) -> dict:
+        st = QbvhServerStats()
+        _check(lib().qbvh_server_stats(self._h, ctypes.byref(st)), "qbvh_server_stats")
+        return {k: getattr(st, k) for k, _ in QbvhServerStats._fields_}
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            lib().qbvh_server_destroy(self._h)
+        self._h = None
+        self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def qbvh_free(tree: Tree) -> None:

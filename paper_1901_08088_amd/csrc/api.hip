@@ -26,25 +26,26 @@ namespace {
 
 thread_local int g_last_hip_error = 0;
 
-int hip_fail(hipError_t e) {
-    g_last_hip_error = (int)e;
-    (void)hipGetLastError();  // clear the sticky launch error
-    return e == hipErrorOutOfMemory ? QBVH_ENOMEM : QBVH_EHIP;
-}
-
 int resolve_opts(const qbvh_opts_t *in, qbvh_opts_t *out) {
     qbvh_opts_t o{};
     if (in) o = *in;
     if (o.leaf_size == 0) o.leaf_size = 1;
     if (o.qbits == 0) o.qbits = 16;
     if (o.block_size == 0) o.block_size = 256;
-    if (o.leaf_size < 1 || o.leaf_size > 8) return QBVH_EINVAL;
-    if (o.qbits < 8 || o.qbits > 16) return QBVH_EINVAL;
-    // the traversal kernel is compiled for at most 256 work-items per group
-    if (o.block_size < 64 || o.block_size > 256 || (o.block_size % 64) != 0) return QBVH_EINVAL;
+    if (!qbi::leaf_ok(o.leaf_size) || !qbi::qbits_ok(o.qbits) || !qbi::block_ok(o.block_size)) return QBVH_EINVAL;
     if (o.validate != 0 && o.validate != 1) return QBVH_EINVAL;
     *out = o;
     return QBVH_OK;
+}
+
+}  // namespace
+
+namespace qbi {
+
+int hip_fail(hipError_t e) {
+    g_last_hip_error = (int)e;
+    (void)hipGetLastError();  // clear the sticky launch error
+    return e == hipErrorOutOfMemory ? QBVH_ENOMEM : QBVH_EHIP;
 }
 
 bool box_ok(const float box[3]) {
@@ -53,9 +54,6 @@ bool box_ok(const float box[3]) {
         if (!(isfinite(box[d]) && box[d] > 0.0f)) return false;
     return true;
 }
-
-// particle runs store the first sorted position in 28 bits
-constexpr int32_t kMaxParticles = (1 << 28) - 1;
 
 // (rc + skin)^2 in fp64 from the fp32 inputs; -1 marks a pair never listed.
 int list_radii(const float *rcut, float skin, int32_t ntypes, const float box[3],
@@ -80,7 +78,20 @@ int list_radii(const float *rcut, float skin, int32_t ntypes, const float box[3]
     return QBVH_OK;
 }
 
-}  // namespace
+void fill_trav_box(TravArgs &a, const float box[3]) {
+    for (int d = 0; d < 3; ++d) {
+        a.L[d] = (double)box[d];
+        a.Lf[d] = box[d];
+    }
+    a.lmax = fmax(a.L[0], fmax(a.L[1], a.L[2]));
+}
+
+}  // namespace qbi
+
+using qbi::box_ok;
+using qbi::hip_fail;
+using qbi::kMaxParticles;
+using qbi::list_radii;
 
 extern "C" {
 
@@ -184,11 +195,7 @@ int nlist_build(const qbvh_t *tree, const float *rcut, float skin, int32_t max_n
     a.nbr = d_nbr;
     a.count = d_count;
     a.overflow = d_overflow;
-    for (int d = 0; d < 3; ++d) {
-        a.L[d] = (double)tree->box[d];
-        a.Lf[d] = tree->box[d];
-    }
-    a.lmax = fmax(a.L[0], fmax(a.L[1], a.L[2]));
+    qbi::fill_trav_box(a, tree->box);
     a.n = tree->n;
     a.ntypes = tree->ntypes;
     a.max_nbr = max_nbr;
@@ -253,35 +260,6 @@ int qbvh_export(const qbvh_t *tree, int32_t what, void *d_dst, size_t dst_bytes,
     if (bytes == 0 || !src) return QBVH_OK;
     hipError_t e = hipMemcpyAsync(d_dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
-    return QBVH_OK;
-}
-
-// Batched form: every system is built and traversed in stream order using a
-// pool of per-system handles kept by the library.
-int nlist_build_many(int32_t nsys, const qbvh_system_t *sys, const qbvh_batch_opts_t *opts, qbvh_stream_t stream) {
-    static thread_local std::vector<qbvh_t *> pool;
-    if (nsys < 0 || (nsys > 0 && !sys)) return QBVH_EINVAL;
-    qbvh_opts_t o{};
-    if (opts) {
-        o.leaf_size = opts->leaf_size;
-        o.qbits = opts->qbits;
-        o.block_size = opts->block_size;
-    }
-    for (int32_t i = 0; i < nsys; ++i) {
-        const qbvh_system_t &y = sys[i];
-        double r2[QBVH_MAX_TYPES * QBVH_MAX_TYPES];
-        if (y.ntypes < 1 || y.ntypes > QBVH_MAX_TYPES || !box_ok(y.box)) return QBVH_EINVAL;
-        int rc = list_radii(y.rcut, y.skin, y.ntypes, y.box, r2);
-        if (rc != QBVH_OK) return rc;
-    }
-    if ((int32_t)pool.size() < nsys) pool.resize(nsys, nullptr);
-    for (int32_t i = 0; i < nsys; ++i) {
-        const qbvh_system_t &y = sys[i];
-        int rc = qbvh_build(&pool[i], y.d_pos, y.d_type, y.n, y.ntypes, y.box, &o, stream);
-        if (rc != QBVH_OK) return rc;
-        rc = nlist_build(pool[i], y.rcut, y.skin, y.max_nbr, y.d_nbr, y.d_count, y.d_overflow, stream);
-        if (rc != QBVH_OK) return rc;
-    }
     return QBVH_OK;
 }
 

@@ -19,37 +19,10 @@
 //   rope of [f, l]   -> record P[l + 1]
 // because in preorder the records before a node are the kept nodes starting
 // before f and its ancestors starting at f.
-#include "qbvh_internal.h"
+#include "build_common.h"
 
 namespace qbi {
 namespace {
-
-constexpr int kBuildThreads = 256;
-constexpr int kMaxDepth = 128;  // > 65, the deepest possible radix tree over 64-bit keys
-
-__device__ __forceinline__ uint32_t spread10(uint32_t v) {
-    v &= 0x3FFu;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-}
-
-// Bin of one coordinate: floor(x * (1023 / L)) in fp64, clamped to [0, 1023].
-__device__ __forceinline__ uint32_t morton_bin(float x, double scale) {
-    double b = floor((double)x * scale);
-    if (!(b >= 0.0)) b = 0.0;  // negative or NaN
-    if (b > 1023.0) b = 1023.0;
-    return (uint32_t)b;
-}
-
-struct Segment {
-    int32_t s, e;
-};
-
-// Particle run [first, first + count), count <= 8, as a negative reference.
-__device__ __forceinline__ int32_t run_ref(int32_t first, int32_t count) { return ~((first << 3) | (count - 1)); }
 
 __device__ __forceinline__ Segment segment_of(uint32_t key, int32_t n, int32_t ntypes,
                                               const uint32_t *__restrict__ type_count) {
@@ -88,9 +61,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_morton(const float *__restric
             if (!ok) atomicOr(err, 1);
         }
         t = t < 0 ? 0 : (t >= ntypes ? ntypes - 1 : t);
-        const uint32_t code = spread10(morton_bin(x, sx)) | (spread10(morton_bin(y, sy)) << 1) |
-                              (spread10(morton_bin(z, sz)) << 2);
-        keys[k] = code | ((uint32_t)t << 30);
+        keys[k] = morton_key(x, y, z, sx, sy, sz, t);
         vals[k] = (uint32_t)k;
         if (ntypes > 1) atomicAdd(&s_cnt[t], 1u);
     }
@@ -113,15 +84,6 @@ __global__ __launch_bounds__(kBuildThreads) void k_gather(const float *__restric
     sorted[k] = p;
 }
 
-// Common-prefix length of the augmented keys (key << 32 | position); -1
-// outside the segment.  Equal keys are told apart by position (Karras's rule).
-__device__ __forceinline__ int delta(const uint32_t *__restrict__ keys, int32_t i, int32_t j, Segment g) {
-    if (j < g.s || j >= g.e) return -1;
-    const uint32_t a = keys[i], b = keys[j];
-    if (a != b) return __clz(a ^ b);
-    return 32 + __clz((uint32_t)(i ^ j));
-}
-
 // Karras's parallel construction: internal node i of a segment covers a
 // range with i at one end; its direction, far end and split are found by
 // exponential then binary search on the common-prefix length.
@@ -140,26 +102,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_karras(const uint32_t *__rest
         if (g.e - g.s == 1) leaf_parent[i] = -1;
         return;
     }
-    const int d = (delta(keys, i, i + 1, g) - delta(keys, i, i - 1, g)) > 0 ? 1 : -1;
-    const int dmin = delta(keys, i, i - d, g);
-    int32_t lmax = 2;
-    while (delta(keys, i, i + lmax * d, g) > dmin) lmax <<= 1;
-    int32_t l = 0;
-    for (int32_t t = lmax >> 1; t >= 1; t >>= 1)
-        if (delta(keys, i, i + (l + t) * d, g) > dmin) l += t;
-    const int32_t j = i + l * d;
-    const int dnode = delta(keys, i, j, g);
-    int32_t s = 0;
-    int32_t t = l;
-    do {
-        t = (t + 1) >> 1;
-        if (delta(keys, i, i + (s + t) * d, g) > dnode) s += t;
-    } while (t > 1);
-    const int32_t gamma = i + s * d + (d < 0 ? -1 : 0);
-    const int32_t f = i < j ? i : j;
-    const int32_t la = i < j ? j : i;
-    const int32_t cl = (f == gamma) ? ~gamma : gamma;
-    const int32_t cr = (la == gamma + 1) ? ~(gamma + 1) : gamma + 1;
+    const KarrasNode r = karras_node(keys, i, g);
+    const int32_t gamma = r.gamma, f = r.f, la = r.l, cl = r.left, cr = r.right;
     left[i] = cl;
     right[i] = cr;
     rf[i] = f;
@@ -347,7 +291,6 @@ __global__ void k_meta(int32_t n, int32_t ntypes, const uint32_t *__restrict__ t
     int32_t s = 0;
     for (int u = 0; u < t; ++u) s += (int32_t)type_count[u];
     const int32_t c = (ntypes == 1) ? n : (int32_t)type_count[t];
-    TreeMeta m;
     float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
     if (c == 1) {
         const float4 p = sorted[s];
@@ -359,40 +302,7 @@ __global__ void k_meta(int32_t n, int32_t ntypes, const uint32_t *__restrict__ t
         lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
         hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
     }
-    double ext = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        m.lo[d] = lo[d];
-        m.hi[d] = hi[d];
-        const double e = (double)hi[d] - (double)lo[d];
-        ext = e > ext ? e : ext;
-    }
-    ext = ext > ext_floor ? ext : ext_floor;
-    m.h = ext / (double)((1 << qbits) - 1);
-    m.inv_h = 1.0 / m.h;
-    m.start = s;
-    m.count = c;
-    m.root = (c > leaf_size) ? (int32_t)P[s] : run_ref(s, c > 0 ? c : 1);
-    m.end = (int32_t)P[s + c];
-    m.pad[0] = m.pad[1] = 0;
-    meta[t] = m;
-}
-
-__device__ __forceinline__ uint32_t quantize_lo(float v, float root, double h, uint32_t qmax) {
-    double q = floor(((double)v - (double)root) / h);
-    if (!(q >= 0.0)) q = 0.0;
-    if (q > (double)qmax) q = (double)qmax;
-    return (uint32_t)q;
-}
-
-__device__ __forceinline__ uint32_t quantize_hi(float v, float root, double h, uint32_t qmax) {
-    double q = ceil(((double)v - (double)root) / h);
-    if (!(q >= 0.0)) q = 0.0;
-    if (q > (double)qmax) q = (double)qmax;
-    return (uint32_t)q;
-}
-
-__device__ __forceinline__ uint32_t quantize_axis(float lo, float hi, float root, double h, uint32_t qmax) {
-    return quantize_lo(lo, root, h, qmax) | (quantize_hi(hi, root, h, qmax) << 16);
+    meta[t] = tree_meta(lo, hi, ext_floor, qbits, s, c, leaf_size, P);
 }
 
 // One record per kept internal node (Karras id i).
@@ -417,47 +327,13 @@ __global__ __launch_bounds__(kBuildThreads) void k_emit(int32_t n, int32_t ntype
     if (i >= g.e - 1) return;  // not an internal node id
     const int32_t f = rf[i], l = rl[i];
     if (l - f + 1 <= leaf_size) return;  // inside a particle run
-    int32_t rank = 0;
-    int32_t u = i;
-    for (int step = 0; step < kMaxDepth; ++step) {
-        const int32_t pp = parent[u];
-        if (pp < 0 || left[pp] != u) break;
-        ++rank;
-        u = pp;
-    }
-    const int32_t at = (int32_t)P[f] + rank;
     const TreeMeta &m = meta[ntypes == 1 ? 0 : (key >> 30)];
-    const uint32_t qmax = (1u << qbits) - 1u;
-    uint32_t w[8];
-    const int32_t ch[2] = {left[i], right[i]};
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-        const int32_t c = ch[side];
-        float4 lo, hi;
-        int32_t ref;
-        if (c < 0) {
-            lo = hi = sorted[~c];
-            ref = run_ref(~c, 1);
-        } else {
-            lo = box_lo[c];
-            hi = box_hi[c];
-            const int32_t cf = rf[c], cl = rl[c];
-            if (cl - cf + 1 > leaf_size)
-                ref = side == 0 ? at + 1 : (int32_t)P[cf];
-            else
-                ref = run_ref(cf, cl - cf + 1);
-        }
-        w[3 * side + 0] = quantize_axis(lo.x, hi.x, m.lo[0], m.h, qmax);
-        w[3 * side + 1] = quantize_axis(lo.y, hi.y, m.lo[1], m.h, qmax);
-        w[3 * side + 2] = quantize_axis(lo.z, hi.z, m.lo[2], m.h, qmax);
-        w[6 + side] = (uint32_t)ref;
-    }
-    records[2 * (int64_t)at] = make_uint4(w[0], w[1], w[2], w[3]);
-    records[2 * (int64_t)at + 1] = make_uint4(w[4], w[5], w[6], w[7]);
-    ropes[at] = (int32_t)P[l + 1];
+    emit_record(i, f, l, m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, qbits, records, ropes);
 }
 
 inline dim3 grid_for(int64_t items) { return dim3((unsigned)((items + kBuildThreads - 1) / kBuildThreads)); }
+
+}  // namespace
 
 int32_t fit_chunks0(int32_t cap) { return (cap + kFitChunk - 1) / kFitChunk; }
 
@@ -478,8 +354,6 @@ hipError_t launch_fit(const Workspace &w, int32_t n, hipStream_t s) {
     }
     return hipGetLastError();
 }
-
-}  // namespace
 
 size_t workspace_bytes(int32_t cap) {
     const size_t c = cap > 0 ? (size_t)cap : 1;

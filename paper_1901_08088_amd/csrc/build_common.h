@@ -1,0 +1,176 @@
+// Device helpers shared by the single-system and batched builds: Morton bins,
+// segment-bounded common prefixes, particle-run references and the outward
+// quantization of box bounds (Section 2.1, Section 2.2).
+#pragma once
+
+#include "qbvh_internal.h"
+
+namespace qbi {
+
+constexpr int kBuildThreads = 256;
+constexpr int kMaxDepth = 128;  // > 65, the deepest possible radix tree over 64-bit keys
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// Bin of one coordinate: floor(x * (1023 / L)) in fp64, clamped to [0, 1023].
+__device__ __forceinline__ uint32_t morton_bin(float x, double scale) {
+    double b = floor((double)x * scale);
+    if (!(b >= 0.0)) b = 0.0;  // negative or NaN
+    if (b > 1023.0) b = 1023.0;
+    return (uint32_t)b;
+}
+
+__device__ __forceinline__ uint32_t morton_key(float x, float y, float z, double sx, double sy, double sz,
+                                               int32_t type) {
+    return spread10(morton_bin(x, sx)) | (spread10(morton_bin(y, sy)) << 1) | (spread10(morton_bin(z, sz)) << 2) |
+           ((uint32_t)type << 30);
+}
+
+struct Segment {
+    int32_t s, e;
+};
+
+// Particle run [first, first + count), count <= 8, as a negative reference.
+__device__ __forceinline__ int32_t run_ref(int32_t first, int32_t count) { return ~((first << 3) | (count - 1)); }
+
+// Common-prefix length of the augmented keys (key << 32 | position); -1
+// outside the segment.  Equal keys are told apart by position (Karras's rule).
+__device__ __forceinline__ int delta(const uint32_t *__restrict__ keys, int32_t i, int32_t j, Segment g) {
+    if (j < g.s || j >= g.e) return -1;
+    const uint32_t a = keys[i], b = keys[j];
+    if (a != b) return __clz(a ^ b);
+    return 32 + __clz((uint32_t)(i ^ j));
+}
+
+struct KarrasNode {
+    int32_t left, right, f, l, gamma;
+};
+
+// Karras's parallel construction for internal node i of segment g (i < g.e - 1):
+// direction, far end and split by exponential then binary search on the
+// common-prefix length.  Children are internal ids or leaves as ~position.
+__device__ __forceinline__ KarrasNode karras_node(const uint32_t *__restrict__ keys, int32_t i, Segment g) {
+    const int d = (delta(keys, i, i + 1, g) - delta(keys, i, i - 1, g)) > 0 ? 1 : -1;
+    const int dmin = delta(keys, i, i - d, g);
+    int32_t lmax = 2;
+    while (delta(keys, i, i + lmax * d, g) > dmin) lmax <<= 1;
+    int32_t l = 0;
+    for (int32_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (delta(keys, i, i + (l + t) * d, g) > dmin) l += t;
+    const int32_t j = i + l * d;
+    const int dnode = delta(keys, i, j, g);
+    int32_t s = 0;
+    int32_t t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (delta(keys, i, i + (s + t) * d, g) > dnode) s += t;
+    } while (t > 1);
+    KarrasNode r;
+    r.gamma = i + s * d + (d < 0 ? -1 : 0);
+    r.f = i < j ? i : j;
+    r.l = i < j ? j : i;
+    r.left = (r.f == r.gamma) ? ~r.gamma : r.gamma;
+    r.right = (r.l == r.gamma + 1) ? ~(r.gamma + 1) : r.gamma + 1;
+    return r;
+}
+
+__device__ __forceinline__ uint32_t quantize_lo(float v, float root, double h, uint32_t qmax) {
+    double q = floor(((double)v - (double)root) / h);
+    if (!(q >= 0.0)) q = 0.0;
+    if (q > (double)qmax) q = (double)qmax;
+    return (uint32_t)q;
+}
+
+__device__ __forceinline__ uint32_t quantize_hi(float v, float root, double h, uint32_t qmax) {
+    double q = ceil(((double)v - (double)root) / h);
+    if (!(q >= 0.0)) q = 0.0;
+    if (q > (double)qmax) q = (double)qmax;
+    return (uint32_t)q;
+}
+
+__device__ __forceinline__ uint32_t quantize_axis(float lo, float hi, float root, double h, uint32_t qmax) {
+    return quantize_lo(lo, root, h, qmax) | (quantize_hi(hi, root, h, qmax) << 16);
+}
+
+// Tree description from the root box (exact fp32 min/max) of a segment.
+__device__ __forceinline__ TreeMeta tree_meta(const float lo[3], const float hi[3], double ext_floor, int32_t qbits,
+                                              int32_t start, int32_t count, int32_t leaf_size,
+                                              const uint32_t *__restrict__ P) {
+    TreeMeta m;
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        m.lo[d] = lo[d];
+        m.hi[d] = hi[d];
+        const double e = (double)hi[d] - (double)lo[d];
+        ext = e > ext ? e : ext;
+    }
+    ext = ext > ext_floor ? ext : ext_floor;
+    m.h = ext / (double)((1 << qbits) - 1);
+    m.inv_h = 1.0 / m.h;
+    m.start = start;
+    m.count = count;
+    m.root = (count > leaf_size) ? (int32_t)P[start] : run_ref(start, count > 0 ? count : 1);
+    m.end = (int32_t)P[start + count];
+    m.pad[0] = m.pad[1] = 0;
+    return m;
+}
+
+// Record of kept internal node i (particle range [f, l] longer than
+// leaf_size): both child boxes quantized against the tree's root box, both
+// child references, written at its preorder position, plus its rope.
+__device__ __forceinline__ void emit_record(int32_t i, int32_t f, int32_t l, const TreeMeta &m,
+                                            const float4 *__restrict__ sorted, const int32_t *__restrict__ left,
+                                            const int32_t *__restrict__ right, const int32_t *__restrict__ rf,
+                                            const int32_t *__restrict__ rl, const int32_t *__restrict__ parent,
+                                            const float4 *__restrict__ box_lo, const float4 *__restrict__ box_hi,
+                                            const uint32_t *__restrict__ P, int32_t leaf_size, int32_t qbits,
+                                            uint4 *__restrict__ records, int32_t *__restrict__ ropes) {
+    // preorder position: kept nodes starting before f, plus the ancestors
+    // that start at f (the chain of nodes of which i is the left child)
+    int32_t rank = 0;
+    int32_t u = i;
+    for (int step = 0; step < kMaxDepth; ++step) {
+        const int32_t pp = parent[u];
+        if (pp < 0 || left[pp] != u) break;
+        ++rank;
+        u = pp;
+    }
+    const int32_t at = (int32_t)P[f] + rank;
+    const uint32_t qmax = (1u << qbits) - 1u;
+    uint32_t w[8];
+    const int32_t ch[2] = {left[i], right[i]};
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int32_t c = ch[side];
+        float4 lo, hi;
+        int32_t ref;
+        if (c < 0) {
+            lo = hi = sorted[~c];
+            ref = run_ref(~c, 1);
+        } else {
+            lo = box_lo[c];
+            hi = box_hi[c];
+            const int32_t cf = rf[c], cl = rl[c];
+            if (cl - cf + 1 > leaf_size)
+                ref = side == 0 ? at + 1 : (int32_t)P[cf];
+            else
+                ref = run_ref(cf, cl - cf + 1);
+        }
+        w[3 * side + 0] = quantize_axis(lo.x, hi.x, m.lo[0], m.h, qmax);
+        w[3 * side + 1] = quantize_axis(lo.y, hi.y, m.lo[1], m.h, qmax);
+        w[3 * side + 2] = quantize_axis(lo.z, hi.z, m.lo[2], m.h, qmax);
+        w[6 + side] = (uint32_t)ref;
+    }
+    records[2 * (int64_t)at] = make_uint4(w[0], w[1], w[2], w[3]);
+    records[2 * (int64_t)at + 1] = make_uint4(w[4], w[5], w[6], w[7]);
+    ropes[at] = (int32_t)P[l + 1];
+}
+
+}  // namespace qbi

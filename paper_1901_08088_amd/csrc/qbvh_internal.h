@@ -8,6 +8,16 @@
 
 namespace qbi {
 
+// Largest s in [0, nseg) with first[s] <= x (first is nondecreasing, first[0] = 0).
+__device__ __forceinline__ int32_t find_seg(const int32_t *__restrict__ first, int32_t nseg, int32_t x) {
+    int32_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Per-type tree description, written on the device after the bottom-up fit.
 struct TreeMeta {
     float lo[3];      // root-node box (exact fp32 min over the type's particles)
@@ -64,21 +74,76 @@ struct TravArgs {
     float Lf[3];
     float pad0;
     double lmax;
-    int32_t n;
+    int32_t n;        // particles of this system
     int32_t ntypes;
     int32_t max_nbr;
-    int32_t pad;
+    int32_t start;    // first sorted position of this system (0 for a single system)
 };
+
+// One system of a batch as the build kernels see it.
+struct SysBuild {
+    const float *pos;      // device float [n][3]
+    const int32_t *type;   // device int32 [n], or nullptr when ntypes == 1
+    int32_t n;
+    int32_t ntypes;
+    int32_t off;           // first position of the system in the concatenation
+    int32_t pad;
+    double scale[3];       // 1023 / L_d (Morton bins)
+    double ext_floor;      // L_max 2^-24 (smallest root extent used for the grid)
+};
+
+// Device pointers and sizes of one batched launch sequence.  Every system s
+// occupies positions [sys_off[s], sys_off[s + 1]) of the concatenated
+// arrays; blk_first, tile_first and tblk_first give the first build block
+// (kBuildThreads items), sort tile and traversal workgroup of each system.
+struct BatchLaunch {
+    Workspace ws;               // sized for the concatenation
+    uint32_t *hist;             // 256 * tiles sort counters
+    uint32_t *scan_part;        // scan partials for max(total + 1, 256 * tiles)
+    const int32_t *sys_off, *blk_first, *tile_first, *tblk_first;  // [nsys + 1] each
+    const SysBuild *sysb;       // [nsys]
+    const TravArgs *trav;       // [nsys]
+    uint32_t *type_count;       // [nsys][QBVH_MAX_TYPES]
+    TreeMeta *meta;             // [nsys][QBVH_MAX_TYPES]
+    int32_t nsys, total, blocks, tiles, tblocks;
+    int32_t leaf_size, qbits, block_size;
+    bool vec4;
+};
+
+// Host helpers shared by the interface files.
+constexpr int32_t kMaxParticles = (1 << 28) - 1;  // particle runs store a sorted position in 28 bits
+inline bool leaf_ok(int32_t v) { return v >= 1 && v <= 8; }
+inline bool qbits_ok(int32_t v) { return v >= 8 && v <= 16; }
+// the traversal kernel is compiled for 64, 128, 192 and 256 work-items per group
+inline bool block_ok(int32_t v) { return v >= 64 && v <= 256 && (v % 64) == 0; }
+int hip_fail(hipError_t e);  // records the error for qbvh_last_hip_error, maps it to a code
+bool box_ok(const float box[3]);
+int list_radii(const float *rcut, float skin, int32_t ntypes, const float box[3],
+               double rlist2[QBVH_MAX_TYPES * QBVH_MAX_TYPES]);
+void fill_trav_box(TravArgs &a, const float box[3]);
 
 // Launchers (all asynchronous on `s`; return the launch status).
 hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d_type, int32_t n,
                         int32_t ntypes, const float box[3], int32_t leaf_size, int32_t qbits,
                         int32_t validate, hipStream_t s);
 hipError_t launch_traverse(const TravArgs &a, int32_t block, bool vec4, hipStream_t s);
+hipError_t launch_traverse_batch(const BatchLaunch &b, hipStream_t s);
+hipError_t launch_batch(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
                              uint32_t *hist, uint32_t *digit_total, int32_t n, int32_t tiles,
                              hipStream_t s);
 hipError_t launch_exclusive_scan(uint32_t *data, int32_t len, uint32_t *partials, hipStream_t s);
+hipError_t launch_fit(const Workspace &w, int32_t n, hipStream_t s);
+int32_t fit_chunks0(int32_t cap);
+// Stable sort of each segment [seg_off[s], seg_off[s+1]) of (keys, vals) on
+// its own; tile_first[s] = sum over earlier segments of seg_radix_tiles(size),
+// tiles = tile_first[nseg]; hist holds 256 * tiles counters, scan_part
+// scan_blocks(256 * tiles) + 1.
+hipError_t launch_radix_sort_segmented(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
+                                       uint32_t *hist, uint32_t *scan_part, int32_t n, int32_t tiles,
+                                       const int32_t *tile_first, const int32_t *seg_off, int32_t nseg,
+                                       hipStream_t s);
+int32_t seg_radix_tiles(int32_t n);
 int32_t radix_tiles(int32_t n);
 int32_t scan_blocks(int32_t len);
 

@@ -58,25 +58,64 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *l
     return wsum + incl - v;
 }
 
+// Tile geometry.  Single array: tile t covers [4096 t, 4096 (t + 1)) and its
+// count of digit d sits at hist[d * tiles + t].  Segmented (a batch of
+// independent arrays laid end to end): tiles never straddle a segment, and
+// the counts of segment s are stored digit-major after those of the segments
+// before it, so one exclusive scan over the whole histogram array yields every
+// tile's output offset for every digit directly (segment start + counts of
+// smaller digits in the segment + counts of the same digit in earlier tiles).
+struct TileView {
+    int64_t base;     // first element of the tile
+    int32_t nvalid;   // elements in the tile
+    int64_t hbase;    // histogram index of digit 0
+    int32_t hstride;  // histogram distance between digits
+};
+
+template <bool kSeg>
+__device__ __forceinline__ TileView tile_view(int32_t tile, int32_t n, int32_t tiles, const int32_t *tile_first,
+                                              const int32_t *seg_off, int32_t nseg) {
+    TileView v;
+    if (!kSeg) {
+        v.base = (int64_t)tile * kSortTile;
+        const int64_t rem = (int64_t)n - v.base;
+        v.nvalid = rem < kSortTile ? (int32_t)rem : kSortTile;
+        v.hbase = tile;
+        v.hstride = tiles;
+    } else {
+        const int32_t s = find_seg(tile_first, nseg, tile);
+        const int32_t lt = tile - tile_first[s];
+        const int32_t ntl = tile_first[s + 1] - tile_first[s];
+        v.base = (int64_t)seg_off[s] + (int64_t)lt * kSortTile;
+        const int64_t rem = (int64_t)seg_off[s + 1] - v.base;
+        v.nvalid = rem < kSortTile ? (int32_t)rem : kSortTile;
+        v.hbase = (int64_t)kRadix * tile_first[s] + lt;
+        v.hstride = ntl;
+    }
+    return v;
+}
+
+template <bool kSeg>
 __global__ __launch_bounds__(kHistThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int32_t n,
                                                              int32_t shift, uint32_t *__restrict__ hist,
-                                                             int32_t tiles) {
+                                                             int32_t tiles, const int32_t *__restrict__ tile_first,
+                                                             const int32_t *__restrict__ seg_off, int32_t nseg) {
     __shared__ uint32_t h[kHistThreads / 64][kRadix];
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
+    const TileView tv = tile_view<kSeg>(blockIdx.x, n, tiles, tile_first, seg_off, nseg);
     for (int i = tid; i < (kHistThreads / 64) * kRadix; i += kHistThreads) (&h[0][0])[i] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll 4
     for (int i = 0; i < kSortTile / kHistThreads; ++i) {
-        int64_t idx = base + (int64_t)i * kHistThreads + tid;
-        if (idx < n) atomicAdd(&h[wave][(keys[idx] >> shift) & (kRadix - 1)], 1u);
+        const int j = i * kHistThreads + tid;
+        if (j < tv.nvalid) atomicAdd(&h[wave][(keys[tv.base + j] >> shift) & (kRadix - 1)], 1u);
     }
     __syncthreads();
     uint32_t c = 0;
 #pragma unroll
     for (int w = 0; w < kHistThreads / 64; ++w) c += h[w][tid];
-    hist[(int64_t)tid * tiles + blockIdx.x] = c;
+    hist[tv.hbase + (int64_t)tid * tv.hstride] = c;
 }
 
 // One workgroup per digit: exclusive scan of that digit's tile counts in place.
@@ -107,10 +146,12 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_digit_scan(uint32_t *__r
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
+template <bool kSeg>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, int32_t n, int32_t shift, const uint32_t *__restrict__ hist,
-    const uint32_t *__restrict__ digit_total, int32_t tiles) {
+    const uint32_t *__restrict__ digit_total, int32_t tiles, const int32_t *__restrict__ tile_first,
+    const int32_t *__restrict__ seg_off, int32_t nseg) {
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
     __shared__ uint32_t s_wcnt[kSortWaves][kRadix];
@@ -121,17 +162,20 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     const int wave = tid >> 6;
-    const int tile = blockIdx.x;
-    const int64_t base = (int64_t)tile * kSortTile;
+    const TileView tv = tile_view<kSeg>(blockIdx.x, n, tiles, tile_first, seg_off, nseg);
+    const int64_t base = tv.base;
 
     for (int i = tid; i < kSortWaves * kRadix; i += kSortThreads) (&s_wcnt[0][0])[i] = 0;
 
-    // Global start of each digit: exclusive scan of the digit totals.
-    {
+    if (!kSeg) {
+        // global start of each digit: exclusive scan of the digit totals
         uint32_t dt = tid < kRadix ? digit_total[tid] : 0u;
         uint32_t tot;
         uint32_t gstart = block_exclusive_scan<kSortThreads>(dt, s_scan, tot);
-        if (tid < kRadix) s_goff[tid] = gstart + hist[(int64_t)tid * tiles + tile];
+        if (tid < kRadix) s_goff[tid] = gstart + hist[tv.hbase + (int64_t)tid * tv.hstride];
+    } else if (tid < kRadix) {
+        // the histogram array has been scanned as a whole: offsets are final
+        s_goff[tid] = hist[tv.hbase + (int64_t)tid * tv.hstride];
     }
     __syncthreads();
 
@@ -139,16 +183,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-        int64_t idx = base + (int64_t)wave * 64 * kSortItems + i * 64 + lane;
-        bool valid = idx < n;
+        const int32_t j = wave * 64 * kSortItems + i * 64 + lane;
+        const bool valid = j < tv.nvalid;
+        const int64_t idx = base + j;
         k[i] = valid ? keys_in[idx] : 0u;
         v[i] = valid ? vals_in[idx] : 0u;
     }
     // Stable rank within the wave's chunk: items in order i, then lane.
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-        int64_t idx = base + (int64_t)wave * 64 * kSortItems + i * 64 + lane;
-        bool valid = idx < n;
+        const bool valid = wave * 64 * kSortItems + i * 64 + lane < tv.nvalid;
         uint32_t d = (k[i] >> shift) & (kRadix - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -186,8 +230,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-        int64_t idx = base + (int64_t)wave * 64 * kSortItems + i * 64 + lane;
-        if (idx < n) {
+        if (wave * 64 * kSortItems + i * 64 + lane < tv.nvalid) {
             uint32_t d = (k[i] >> shift) & (kRadix - 1);
             uint32_t p = s_dstart[d] + s_wcnt[wave][d] + r[i];
             s_keys[p] = k[i];
@@ -196,9 +239,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
     __syncthreads();
 
-    const int64_t rem = (int64_t)n - base;
-    const int nvalid = rem < kSortTile ? (int)rem : kSortTile;
-    for (int j = tid; j < nvalid; j += kSortThreads) {
+    for (int j = tid; j < tv.nvalid; j += kSortThreads) {
         uint32_t key = s_keys[j];
         uint32_t d = (key >> shift) & (kRadix - 1);
         uint32_t g = s_goff[d] + (uint32_t)j - s_dstart[d];
@@ -268,10 +309,11 @@ hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, ui
     uint32_t *ki = keys, *vi = vals, *ko = keys2, *vo = vals2;
     for (int pass = 0; pass < 32 / kRadixBits; ++pass) {
         const int shift = pass * kRadixBits;
-        hipLaunchKernelGGL(k_radix_hist, dim3(t), dim3(kHistThreads), 0, s, ki, n, shift, hist, t);
+        hipLaunchKernelGGL(k_radix_hist<false>, dim3(t), dim3(kHistThreads), 0, s, ki, n, shift, hist, t,
+                           nullptr, nullptr, 0);
         hipLaunchKernelGGL(k_radix_digit_scan, dim3(kRadix), dim3(kScanThreads), 0, s, hist, t, digit_total);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(t), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift, hist,
-                           digit_total, t);
+        hipLaunchKernelGGL(k_radix_scatter<false>, dim3(t), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift,
+                           hist, digit_total, t, nullptr, nullptr, 0);
         uint32_t *tk = ki, *tv = vi;
         ki = ko;
         vi = vo;
@@ -280,6 +322,31 @@ hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, ui
     }
     // An even number of passes leaves the result in (keys, vals).
     static_assert((32 / kRadixBits) % 2 == 0, "result must end in the primary buffers");
+    return hipGetLastError();
+}
+
+int32_t seg_radix_tiles(int32_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+hipError_t launch_radix_sort_segmented(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
+                                       uint32_t *hist, uint32_t *scan_part, int32_t n, int32_t tiles,
+                                       const int32_t *tile_first, const int32_t *seg_off, int32_t nseg,
+                                       hipStream_t s) {
+    if (n <= 1 || tiles <= 0) return hipSuccess;
+    uint32_t *ki = keys, *vi = vals, *ko = keys2, *vo = vals2;
+    for (int pass = 0; pass < 32 / kRadixBits; ++pass) {
+        const int shift = pass * kRadixBits;
+        hipLaunchKernelGGL(k_radix_hist<true>, dim3(tiles), dim3(kHistThreads), 0, s, ki, n, shift, hist, tiles,
+                           tile_first, seg_off, nseg);
+        hipError_t e = launch_exclusive_scan(hist, kRadix * tiles, scan_part, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter<true>, dim3(tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift,
+                           hist, nullptr, tiles, tile_first, seg_off, nseg);
+        uint32_t *tk = ki, *tv = vi;
+        ki = ko;
+        vi = vo;
+        ko = tk;
+        vo = tv;
+    }
     return hipGetLastError();
 }
 

@@ -41,18 +41,32 @@
 namespace qbi {
 namespace {
 
-// The bias 0x4B000000 lives in a VGPR (opaque to the compiler) so that a
-// record word held in an SGPR is decoded by one VALU op (v_or_b32 with a
-// 16-bit source select) instead of two scalar ops: the scalar unit, not the
-// vector ALU, is the scarce issue slot of the shared walk.
+// Decoding a 16-bit bound q of a record word held in a scalar register: the
+// float with bits 0x4B000000 | q is exactly 2^23 + q.  One VALU op per bound
+// (v_or_b32 with a 16-bit source select of the scalar word against the bias
+// held in a VGPR) keeps the decode off the scalar unit, which is the other
+// scarce issue slot of the shared walk.
 __device__ __forceinline__ uint32_t vgpr_bias() {
     uint32_t v;
     asm volatile("v_mov_b32 %0, 0x4b000000" : "=v"(v));
     return v;
 }
 
-__device__ __forceinline__ float lo_bound(uint32_t w, uint32_t bias) { return __uint_as_float(bias | (w & 0xFFFFu)); }
-__device__ __forceinline__ float hi_bound(uint32_t w, uint32_t bias) { return __uint_as_float(bias | (w >> 16)); }
+__device__ __forceinline__ float lo_bound(uint32_t w, uint32_t bias) {
+    float r;
+    asm("v_or_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:DWORD"
+        : "=v"(r)
+        : "s"(w), "v"(bias));
+    return r;
+}
+
+__device__ __forceinline__ float hi_bound(uint32_t w, uint32_t bias) {
+    float r;
+    asm("v_or_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:DWORD"
+        : "=v"(r)
+        : "s"(w), "v"(bias));
+    return r;
+}
 
 // Squared grid-unit distance from the query (ux, uy, uz) to a packed box.
 __device__ __forceinline__ float box_d2(uint32_t wx, uint32_t wy, uint32_t wz, float ux, float uy, float uz,
@@ -65,21 +79,16 @@ __device__ __forceinline__ float box_d2(uint32_t wx, uint32_t wy, uint32_t wz, f
 
 __device__ __forceinline__ int32_t uniform(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// Output row writer.  With 16-byte aligned rows the lane stages four indices
-// in its LDS column and writes them with one 16-byte store.
-template <bool kVec4, int kBlock>
-__device__ __forceinline__ void append(int32_t j, int32_t &cnt, int32_t (*s_out)[kBlock], int32_t *nbr,
-                                       int32_t orig, int32_t max_nbr) {
-    if (kVec4) {
-        s_out[cnt & 3][threadIdx.x] = j;
-        if ((cnt & 3) == 3 && cnt < max_nbr)
-            *reinterpret_cast<int4 *>(nbr + ((int64_t)orig * max_nbr + (cnt - 3))) =
-                make_int4(s_out[0][threadIdx.x], s_out[1][threadIdx.x], s_out[2][threadIdx.x], j);
-    } else {
-        if (cnt < max_nbr) nbr[(int64_t)orig * max_nbr + cnt] = j;
-    }
-    ++cnt;
-}
+// Row staging.  Each lane keeps its newest list entries in a ring of kRing
+// LDS slots (its own column, so lanes never share a bank row) and writes them
+// to its row kFlush at a time: with 16-byte aligned rows as two 16-byte
+// stores.  A candidate's index is written to the lane's next free slot
+// whether or not it is accepted, and the count advances only on acceptance,
+// so the per-candidate path has no branch.  A run holds at most 8 particles
+// and the ring is flushed after every run once kFlush entries wait, so no
+// more than 15 entries are ever pending.
+constexpr int kRing = 16;
+constexpr int kFlush = 8;
 
 struct Lane {
     float x, y, z;         // query position
@@ -89,20 +98,40 @@ struct Lane {
     float r2in, r2out;     // fp32 accept / reject thresholds
     double r2;             // exact squared list radius
     int32_t k, orig;
+    int32_t cnt;           // entries of the list so far
+    int32_t flushed;       // entries already written to the row (a multiple of kFlush)
 };
 
-// Decide the particles of one hit run for the lanes with `hit` set.
 template <bool kVec4, int kBlock>
-__device__ __forceinline__ void take_run(int32_t ref, bool hit, const Lane &q, int img, const double (&L)[3],
-                                         const float4 *__restrict__ sorted, uint32_t n, int32_t &cnt,
-                                         int32_t (*s_out)[kBlock], int32_t *nbr, int32_t max_nbr) {
-    const int32_t v = ~ref;
-    const uint32_t first = (uint32_t)uniform(v >> 3);
-    const uint32_t count = (uint32_t)uniform((v & 7) + 1);
-    // a well-formed tree never fails this; it keeps a corrupt reference from
-    // reading outside the particle array
-    if (first + count > n) return;
-    const float4 *run = sorted + first;
+__device__ __forceinline__ void flush_ring(Lane &q, int32_t (*s_out)[kBlock], int32_t *nbr, int32_t max_nbr) {
+    const int32_t f = q.flushed;
+    const int s0 = f & (kRing - 1);
+    int32_t *row = nbr + ((int64_t)q.orig * max_nbr + f);
+    if (kVec4) {
+        // f and max_nbr are multiples of 4 here
+        if (f + 4 <= max_nbr)
+            *reinterpret_cast<int4 *>(row) = make_int4(s_out[s0][threadIdx.x], s_out[s0 + 1][threadIdx.x],
+                                                       s_out[s0 + 2][threadIdx.x], s_out[s0 + 3][threadIdx.x]);
+        if (f + 8 <= max_nbr)
+            *reinterpret_cast<int4 *>(row + 4) = make_int4(s_out[s0 + 4][threadIdx.x], s_out[s0 + 5][threadIdx.x],
+                                                           s_out[s0 + 6][threadIdx.x], s_out[s0 + 7][threadIdx.x]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < kFlush; ++e)
+            if (f + e < max_nbr) row[e] = s_out[s0 + e][threadIdx.x];
+    }
+    q.flushed = f + kFlush;
+}
+
+// fp32 pass over up to 8 particles of a run for every lane.  Accepts what is
+// surely in (d2 <= thr; thr = r2in for hitting lanes, -1 otherwise) and
+// returns whether some lane saw a pair in the shell (thr, out] that needs the
+// exact test (out = r2out for hitting lanes, -1 otherwise).  kSelf: the run
+// may hold the lane's own particle at index `rel`, which is never listed.
+template <bool kSelf, int kBlock>
+__device__ __forceinline__ bool run_fp32(const float4 *__restrict__ run, uint32_t count, uint32_t rel, float thr,
+                                         float out, Lane &q, int32_t (*s_out)[kBlock]) {
+    bool shell = false;
     for (uint32_t j0 = 0; j0 < count; j0 += 4) {
         // up to four uniform loads issued before any use
         float4 p[4];
@@ -112,42 +141,113 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, const Lane &q, i
         for (int u = 0; u < 4; ++u) {
             if (j0 + u >= count) break;
             const float ax = p[u].x - q.qsx, ay = p[u].y - q.qsy, az = p[u].z - q.qsz;
-            const float d2f = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
-            bool in = hit && d2f <= q.r2in;
-            const bool amb = hit && !in && d2f <= q.r2out;
-            if (__any(amb) && amb) {
-                // shell around the cutoff: the definition's fp64 arithmetic
-                const double sx = (double)(img % 3 - 1) * L[0];
-                const double sy = (double)((img / 3) % 3 - 1) * L[1];
-                const double sz = (double)(img / 9 - 1) * L[2];
-                const double dx = ((double)p[u].x - (double)q.x) - sx;
-                const double dy = ((double)p[u].y - (double)q.y) - sy;
-                const double dz = ((double)p[u].z - (double)q.z) - sz;
-                in = (dx * dx + dy * dy) + dz * dz <= q.r2;
-            }
-            if (in && (int32_t)(first + j0 + u) != q.k)
-                append<kVec4, kBlock>(~__float_as_int(p[u].w), cnt, s_out, nbr, q.orig, max_nbr);
+            const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
+            bool acc = d2 <= thr;
+            shell = shell || (!acc && d2 <= out);
+            if (kSelf) acc = acc && (j0 + u != rel);
+            s_out[q.cnt & (kRing - 1)][threadIdx.x] = ~__float_as_int(p[u].w);
+            q.cnt += acc ? 1 : 0;
         }
     }
+    return shell;
+}
+
+// Decide the particles of one hit run for the lanes with `hit` set.
+template <bool kVec4, int kBlock>
+__device__ __forceinline__ void take_run(int32_t ref, bool hit, Lane &q, int img, const double (&L)[3],
+                                         const float4 *__restrict__ sorted, uint32_t nend,
+                                         int32_t (*s_out)[kBlock], int32_t *nbr, int32_t max_nbr) {
+    const int32_t v = ~ref;
+    const uint32_t first = (uint32_t)uniform(v >> 3);
+    const uint32_t count = (uint32_t)uniform((v & 7) + 1);
+    // a well-formed tree never fails this; it keeps a corrupt reference from
+    // reading outside the particle array
+    if (first + count > nend) return;
+    const float4 *run = sorted + first;
+    const float thr = hit ? q.r2in : -1.0f;
+    // the lane's own particle can only be accepted through the unshifted image
+    const uint32_t rel = (uint32_t)(q.k - (int32_t)first);
+    const float out = hit ? q.r2out : -1.0f;
+    const bool self = img == 13 && __any(hit && rel < count);
+    const bool shell = self ? run_fp32<true, kBlock>(run, count, rel, thr, out, q, s_out)
+                            : run_fp32<false, kBlock>(run, count, rel, thr, out, q, s_out);
+    if (__any(shell)) {
+        // some pair lies in the shell around the cutoff: decide the shell
+        // pairs with the definition's fp64 arithmetic
+        const double sx = (double)(img % 3 - 1) * L[0];
+        const double sy = (double)((img / 3) % 3 - 1) * L[1];
+        const double sz = (double)(img / 9 - 1) * L[2];
+        for (uint32_t j = 0; j < count; ++j) {
+            const float4 p = run[j];
+            const float ax = p.x - q.qsx, ay = p.y - q.qsy, az = p.z - q.qsz;
+            const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
+            if (hit && !(d2 <= thr) && d2 <= q.r2out && j != rel) {
+                const double dx = ((double)p.x - (double)q.x) - sx;
+                const double dy = ((double)p.y - (double)q.y) - sy;
+                const double dz = ((double)p.z - (double)q.z) - sz;
+                if ((dx * dx + dy * dy) + dz * dz <= q.r2) {
+                    s_out[q.cnt & (kRing - 1)][threadIdx.x] = ~__float_as_int(p.w);
+                    ++q.cnt;
+                }
+            }
+        }
+    }
+    if (__any(q.cnt - q.flushed >= kFlush) && q.cnt - q.flushed >= kFlush) flush_ring<kVec4, kBlock>(q, s_out, nbr, max_nbr);
 }
 
 // The read-only arrays come as separate __restrict__ parameters: that lets the
 // compiler fetch wave-uniform records and particles with scalar loads.
 template <bool kVec4, int kBlock>
+__device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local, const uint4 *__restrict__ records,
+                                               const int32_t *__restrict__ ropes,
+                                               const float4 *__restrict__ sorted,
+                                               const TreeMeta *__restrict__ meta, int32_t (*s_out)[kBlock]);
+
+// Workgroups are dealt round-robin to the 8 XCDs; each XCD gets one
+// contiguous stretch of the Z-ordered queries so its L2 holds one region.
+__device__ __forceinline__ int32_t xcd_logical_block() {
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t xcd = b & 7u, qq = nb >> 3, rr = nb & 7u;
+    return (int32_t)(xcd * qq + (xcd < rr ? xcd : rr) + (b >> 3));
+}
+
+template <bool kVec4, int kBlock>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_traverse(
     TravArgs a, const uint4 *__restrict__ records, const int32_t *__restrict__ ropes,
     const float4 *__restrict__ sorted, const TreeMeta *__restrict__ meta) {
-    __shared__ int32_t s_out[4][kBlock];
-    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
-    // contiguous stretch of the Z-ordered queries so its L2 holds one region.
-    const uint32_t nb = gridDim.x, b = blockIdx.x;
-    const uint32_t xcd = b & 7u, qq = nb >> 3, rr = nb & 7u;
-    const uint32_t logical = xcd * qq + (xcd < rr ? xcd : rr) + (b >> 3);
-    const int32_t k = (int32_t)(logical * kBlock + threadIdx.x);
-    const bool valid = k < a.n;  // idle lanes still take part in the shared walk
+    __shared__ int32_t s_out[kRing][kBlock];
+    traverse_block<kVec4, kBlock>(a, xcd_logical_block(), records, ropes, sorted, meta, s_out);
+}
+
+// Batched form: the workgroups of all systems form one grid; each workgroup
+// belongs to one system (found from the per-system first-workgroup table) and
+// reads that system's arguments from the device table, so every per-system
+// value stays wave-uniform.
+template <bool kVec4, int kBlock>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_traverse_batch(
+    const TravArgs *__restrict__ table, const int32_t *__restrict__ tblk_first, int32_t nsys,
+    const uint4 *__restrict__ records, const int32_t *__restrict__ ropes, const float4 *__restrict__ sorted,
+    const TreeMeta *__restrict__ meta_all) {
+    __shared__ int32_t s_out[kRing][kBlock];
+    const int32_t logical = xcd_logical_block();
+    const int32_t sys = find_seg(tblk_first, nsys, logical);
+    traverse_block<kVec4, kBlock>(table[sys], logical - tblk_first[sys], records, ropes, sorted,
+                                  meta_all + sys * QBVH_MAX_TYPES, s_out);
+}
+
+// One workgroup of queries: local workgroup `local` of the system `a`.
+template <bool kVec4, int kBlock>
+__device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local, const uint4 *__restrict__ records,
+                                               const int32_t *__restrict__ ropes,
+                                               const float4 *__restrict__ sorted,
+                                               const TreeMeta *__restrict__ meta, int32_t (*s_out)[kBlock]) {
+    const int32_t li = local * kBlock + (int32_t)threadIdx.x;
+    const bool valid = li < a.n;  // idle lanes still take part in the shared walk
+    const int32_t k = a.start + li;
+    const uint32_t nend = (uint32_t)(a.start + a.n);
 
     Lane q;
-    const float4 qp = sorted[valid ? k : 0];
+    const float4 qp = sorted[valid ? k : a.start];
     q.x = qp.x;
     q.y = qp.y;
     q.z = qp.z;
@@ -157,7 +257,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     for (int t = 1; t < a.ntypes; ++t)
         if (k >= meta[t].start) ta = t;
 
-    int32_t cnt = 0;
+    q.cnt = 0;
+    q.flushed = 0;
     const uint32_t bias = vgpr_bias();
     for (int tb = 0; tb < a.ntypes; ++tb) {
         const TreeMeta &m = meta[tb];
@@ -225,8 +326,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
             q.uy = (float)((((double)q.y + sy) - (double)m.lo[1]) * m.inv_h + 8388608.0);
             q.uz = (float)((((double)q.z + sz) - (double)m.lo[2]) * m.inv_h + 8388608.0);
             if (root < 0) {  // a tree of at most leaf_size particles is one run
-                take_run<kVec4, kBlock>(root, on, q, img, a.L, sorted, (uint32_t)a.n, cnt, s_out, a.nbr,
-                                        a.max_nbr);
+                take_run<kVec4, kBlock>(root, on, q, img, a.L, sorted, nend, s_out, a.nbr, a.max_nbr);
                 continue;
             }
             int32_t v = root;
@@ -239,11 +339,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
                 const bool anyl = __any(hl), anyr = __any(hr);
                 const int32_t cl = (int32_t)r1.z, cr = (int32_t)r1.w;
                 if (cl < 0 && anyl)
-                    take_run<kVec4, kBlock>(cl, hl, q, img, a.L, sorted, (uint32_t)a.n, cnt, s_out, a.nbr,
-                                            a.max_nbr);
+                    take_run<kVec4, kBlock>(cl, hl, q, img, a.L, sorted, nend, s_out, a.nbr, a.max_nbr);
                 if (cr < 0 && anyr)
-                    take_run<kVec4, kBlock>(cr, hr, q, img, a.L, sorted, (uint32_t)a.n, cnt, s_out, a.nbr,
-                                            a.max_nbr);
+                    take_run<kVec4, kBlock>(cr, hr, q, img, a.L, sorted, nend, s_out, a.nbr, a.max_nbr);
                 const int32_t next = (anyl && cl >= 0) ? cl : ((anyr && cr >= 0) ? cr : rope);
                 // references always point forward; max() makes progress unconditional
                 v = uniform(max(next, v + 1));
@@ -252,16 +350,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     }
 
     if (!valid) return;
-    a.count[q.orig] = cnt;
-    if (kVec4) {
-        const int32_t rem = cnt & 3;
-        const int32_t at = cnt - rem;
-        if (rem && at < a.max_nbr) {
-            int32_t *row = a.nbr + (int64_t)q.orig * a.max_nbr;
-            for (int32_t e = 0; e < rem; ++e) row[at + e] = s_out[e][threadIdx.x];
-        }
-    }
-    if (cnt > a.max_nbr) atomicOr(a.overflow, 1);
+    a.count[q.orig] = q.cnt;
+    // the last (fewer than kFlush) entries
+    const int32_t f = q.flushed, s0 = f & (kRing - 1);
+    int32_t *row = a.nbr + ((int64_t)q.orig * a.max_nbr + f);
+    for (int32_t e = 0; e < q.cnt - f; ++e)
+        if (f + e < a.max_nbr) row[e] = s_out[(s0 + e) & (kRing - 1)][threadIdx.x];
+    if (q.cnt > a.max_nbr) atomicOr(a.overflow, 1);
 }
 
 __global__ void k_clear_flag(int32_t *f) {
@@ -275,6 +370,12 @@ void launch_one(const TravArgs &a, hipStream_t s) {
                        a.meta);
 }
 
+template <bool kVec4, int kBlock>
+void launch_one_batch(const BatchLaunch &b, hipStream_t s) {
+    hipLaunchKernelGGL((k_traverse_batch<kVec4, kBlock>), dim3((unsigned)b.tblocks), dim3(kBlock), 0, s, b.trav,
+                       b.tblk_first, b.nsys, b.ws.records, b.ws.ropes, b.ws.sorted, b.meta);
+}
+
 template <bool kVec4>
 void launch_block(const TravArgs &a, int32_t block, hipStream_t s) {
     switch (block) {
@@ -282,6 +383,16 @@ void launch_block(const TravArgs &a, int32_t block, hipStream_t s) {
     case 128: launch_one<kVec4, 128>(a, s); break;
     case 192: launch_one<kVec4, 192>(a, s); break;
     default: launch_one<kVec4, 256>(a, s); break;
+    }
+}
+
+template <bool kVec4>
+void launch_block_batch(const BatchLaunch &b, hipStream_t s) {
+    switch (b.block_size) {
+    case 64: launch_one_batch<kVec4, 64>(b, s); break;
+    case 128: launch_one_batch<kVec4, 128>(b, s); break;
+    case 192: launch_one_batch<kVec4, 192>(b, s); break;
+    default: launch_one_batch<kVec4, 256>(b, s); break;
     }
 }
 
@@ -294,6 +405,17 @@ hipError_t launch_traverse(const TravArgs &a, int32_t block, bool vec4, hipStrea
             launch_block<true>(a, block, s);
         else
             launch_block<false>(a, block, s);
+    }
+    return hipGetLastError();
+}
+
+// The overflow flags of a batch are cleared by the batch's first kernel.
+hipError_t launch_traverse_batch(const BatchLaunch &b, hipStream_t s) {
+    if (b.tblocks > 0) {
+        if (b.vec4)
+            launch_block_batch<true>(b, s);
+        else
+            launch_block_batch<false>(b, s);
     }
     return hipGetLastError();
 }

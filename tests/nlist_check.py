@@ -85,3 +85,35 @@ def export(tree, what, n, dtype, width=1):
     torch.cuda.synchronize()
     a = t.cpu().numpy()
     return a[:n]
+
+
+def batch_buffers(cfgs, max_nbr=256, fill=-7):
+    """Device inputs and fresh output buffers for nlist_build_many, one dict per system."""
+    torch = require_gpu()
+    systems = []
+    for c in cfgs:
+        pos, types = to_dev(c)
+        n = c.n
+        systems.append(dict(pos=pos, types=types, ntypes=c.ntypes, box=c.box, rcut=c.rcut, skin=c.skin,
+                            max_nbr=max_nbr,
+                            nbr=torch.full((max(n, 1), max(max_nbr, 1)), fill, dtype=torch.int32, device="cuda"),
+                            count=torch.full((max(n, 1),), -1, dtype=torch.int32, device="cuda"),
+                            overflow=torch.full((1,), -1, dtype=torch.int32, device="cuda")))
+    return systems
+
+
+def batch_results(systems, cfgs, rows=None):
+    """Host copies (nbr, count, overflow) of every system; ``rows`` limits the copied rows."""
+    torch = require_gpu()
+    torch.cuda.synchronize()
+    out = []
+    for s, c in zip(systems, cfgs):
+        n, m = c.n, s["max_nbr"]
+        cnt = s["count"].cpu().numpy()[:n]
+        if rows is None:
+            nbr = s["nbr"].cpu().numpy()[:n, :m]
+        else:
+            idx = torch.as_tensor(np.asarray(rows[c.name] if isinstance(rows, dict) else rows), device="cuda")
+            nbr = s["nbr"].index_select(0, idx.long()).cpu().numpy()[:, :m]
+        out.append((nbr, cnt, int(s["overflow"].item())))
+    return out

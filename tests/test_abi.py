@@ -92,6 +92,60 @@ def test_batch_rejects_bad_counts():
     lib = Q.lib()
     assert lib.nlist_build_many(-1, None, None, None) == capi.EINVAL
     assert lib.nlist_build_many(3, None, None, None) == capi.EINVAL
+    assert lib.nlist_build_many(0, None, None, None) == capi.OK
+
+
+def _batch_rc(opts=None, **over):
+    """nlist_build_many on two systems with placeholder device pointers: every
+    case below is rejected by the host checks, before any device work."""
+    lib = Q.lib()
+    arr = (capi.QbvhSystem * 2)()
+    rcs = []
+    for i in range(2):
+        y = arr[i]
+        f = dict(n=100, ntypes=1, box=(10.0, 10.0, 10.0), rcut=[3.0], skin=0.4, max_nbr=64, pos=16, nbr=16,
+                 count=16, overflow=16, typ=0)
+        if i == 1:
+            f.update(over)
+        rc = (ctypes.c_float * len(f["rcut"]))(*f["rcut"])
+        rcs.append(rc)
+        y.d_pos = f["pos"] or None
+        y.d_type = f["typ"] or None
+        y.n = f["n"]
+        y.ntypes = f["ntypes"]
+        for d in range(3):
+            y.box[d] = f["box"][d]
+        y.rcut = ctypes.cast(rc, ctypes.c_void_p)
+        y.skin = f["skin"]
+        y.max_nbr = f["max_nbr"]
+        y.d_nbr = f["nbr"] or None
+        y.d_count = f["count"] or None
+        y.d_overflow = f["overflow"] or None
+    o = capi.QbvhBatchOpts(**opts) if opts else None
+    return lib.nlist_build_many(2, arr, ctypes.byref(o) if o is not None else None, None)
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(n=-1), capi.EINVAL),
+    (dict(n=1 << 28), capi.EINVAL),
+    (dict(ntypes=0), capi.EINVAL),
+    (dict(ntypes=2, rcut=[3.0, 2.0, 2.5, 3.0]), capi.EINVAL),  # types missing and rcut not symmetric
+    (dict(box=(10.0, -1.0, 10.0)), capi.EINVAL),
+    (dict(skin=-0.1), capi.EINVAL),
+    (dict(max_nbr=-1), capi.EINVAL),
+    (dict(pos=0), capi.EINVAL),
+    (dict(count=0), capi.EINVAL),
+    (dict(overflow=0), capi.EINVAL),
+    (dict(nbr=0), capi.EINVAL),
+    (dict(rcut=[4.8]), capi.EGEOM),  # 2 * (4.8 + 0.4) >= 10
+])
+def test_batch_rejects_bad_systems_without_device_work(over, code):
+    assert _batch_rc(**over) == code
+
+
+@pytest.mark.parametrize("opts", [dict(leaf_size=9), dict(qbits=17), dict(block_size=96), dict(eager=2)])
+def test_batch_rejects_bad_options_without_device_work(opts):
+    assert _batch_rc(opts) == capi.EINVAL
 
 
 def test_package_does_not_import_the_oracle():

@@ -313,3 +313,38 @@ def slab(n_target_liquid_thickness: float = 80.0, seed=SEEDS["served"], box=(60.
     return Config(pos=pos, box=box32, rcut=np.array([[rc]], dtype=np.float32), skin=skin,
                   name=f"slab_t{t:g}_N{pos.shape[0]}",
                   meta={"seed": seed, "n_liquid": liq.shape[0], "n_vapor": n_vap})
+
+
+def served_sims(n_sims: int = 64, n_slabs: int = 16, seed=SEEDS["served"], n_min: int = 10_000,
+                n_max: int = 2_000_000, scale: float = 1.0) -> list[Config]:
+    """The simulations behind the served stream: ``n_slabs`` liquid-vapor slabs
+    (box 60 x 60 x 240, liquid thickness chosen so N is log-uniform in
+    [n_min, n_max] within what the box allows) and Lennard-Jones fluids
+    (density 0.85, N log-uniform in [n_min, n_max]); rc 3.0 + skin 0.4.
+
+    ``scale`` shrinks every N (and the slab box edges by its cube root) for
+    test-sized streams without changing the draws.
+    """
+    children = np.random.SeedSequence(seed).spawn(n_sims)
+    out = []
+    for k, ss in enumerate(children):
+        rng = np.random.default_rng(ss)
+        n = float(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))) * scale
+        sub = int(rng.integers(0, 2 ** 63 - 1))
+        if k < n_slabs:
+            f = scale ** (1.0 / 3.0)
+            box = (60.0 * f, 60.0 * f, 240.0 * f)
+            area = box[0] * box[1]
+            # N = area (0.8 t + 0.02 (Lz - t))  =>  t
+            t = (n / area - 0.02 * box[2]) / 0.78
+            t = float(min(max(t, 4.0), box[2] - 2.0))
+            c = slab(t, seed=sub, box=box)
+            c.name = f"sim{k}_{c.name}"
+        else:
+            n_i = max(200, int(round(n)))
+            c = lj_fluid(n_i, seed=sub)
+            c.name = f"sim{k}_lj_N{n_i}"
+        c.meta = dict(c.meta, sim=k)
+        out.append(c)
+    return out
+
