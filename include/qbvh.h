@@ -78,8 +78,8 @@ enum {
 typedef struct {
     int32_t leaf_size;  /* particles per leaf run: a subtree with at most this many
                            particles is not split further and its particles are
-                           tested one by one (1..8, default 1 = one particle per
-                           leaf as in the paper) */
+                           tested one by one (1..8, default 8; 1 gives one particle
+                           per leaf as in the paper) */
     int32_t qbits;      /* grid bits per axis for the quantized bounds (8..16,
                            default 16; the paper's layout uses 10) */
     int32_t block_size; /* traversal workgroup size: 64, 128, 192 or 256

@@ -284,7 +284,7 @@ class _DeviceArray:
     (torch wraps it without copying)."""
 
     def __init__(self, ptr: int, shape, typestr: str = "<i4"):
-        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, True),
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, False),
                                          "version": 3, "strides": None}
 
 

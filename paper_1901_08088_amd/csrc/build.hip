@@ -132,7 +132,9 @@ __global__ __launch_bounds__(kBuildThreads) void k_karras(const uint32_t *__rest
 // border chains of the tree (each at most 65 deep), so kFrontierCap suffices.
 constexpr int kFitChunk = 2048;
 constexpr int kFitThreads = 1024;
-constexpr int kFitFanout = 256;
+// A small fanout keeps every level's climbs short (about four tree levels from
+// each frontier node) and its workgroups many; N = 8M takes three level launches.
+constexpr int kFitFanout = 16;
 constexpr int kFrontierCap = 160;
 
 __device__ __forceinline__ void frontier_push(int32_t c, uint32_t *s_fcount, int32_t *s_front, int32_t *err) {
@@ -143,6 +145,9 @@ __device__ __forceinline__ void frontier_push(int32_t c, uint32_t *s_fcount, int
         atomicOr(err, 2);
 }
 
+// First level: the chunk's node links, its particles' positions, the visit
+// counters and the boxes all live in LDS (loaded with coalesced reads), so a
+// climb touches global memory only to read its leaf's parent.
 __global__ __launch_bounds__(kFitThreads) void k_fit_local(const float4 *__restrict__ sorted,
                                                            const int32_t *__restrict__ left,
                                                            const int32_t *__restrict__ right,
@@ -154,41 +159,60 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_local(const float4 *__restr
                                                            int32_t *__restrict__ front, uint32_t *__restrict__ fcount,
                                                            int32_t *err) {
     __shared__ float s_box[6][kFitChunk];
+    __shared__ float s_pos[3][kFitChunk];
+    __shared__ int32_t s_link[5][kFitChunk];  // left, right, range first, range last, parent
     __shared__ uint32_t s_visit[kFitChunk];
     __shared__ int32_t s_front[kFrontierCap];
     __shared__ uint32_t s_fcount;
     const int32_t c0 = blockIdx.x * kFitChunk;
-    const int32_t c1 = min(c0 + kFitChunk, n);
-    for (int i = threadIdx.x; i < kFitChunk; i += kFitThreads) s_visit[i] = 0;
+    const int32_t m = min(kFitChunk, n - c0);
+    for (int i = threadIdx.x; i < kFitChunk; i += kFitThreads) {
+        s_visit[i] = 0;
+        if (i < m) {
+            // entries of ids that are not internal nodes (the last position of
+            // a segment) are loaded but never referenced
+            const int32_t k = c0 + i;
+            s_link[0][i] = left[k];
+            s_link[1][i] = right[k];
+            s_link[2][i] = rf[k];
+            s_link[3][i] = rl[k];
+            s_link[4][i] = parent[k];
+            const float4 q = sorted[k];
+            s_pos[0][i] = q.x;
+            s_pos[1][i] = q.y;
+            s_pos[2][i] = q.z;
+        }
+    }
     if (threadIdx.x == 0) s_fcount = 0;
     __syncthreads();
-    for (int32_t k = c0 + threadIdx.x; k < c1; k += kFitThreads) {
-        int32_t c = ~k;
-        int32_t p = leaf_parent[k];
+    for (int32_t i0 = threadIdx.x; i0 < m; i0 += kFitThreads) {
+        int32_t c = ~(c0 + i0);
+        int32_t p = leaf_parent[c0 + i0];
         for (int step = 0; p >= 0 && step < kMaxDepth; ++step) {
-            if (rf[p] < c0 || rl[p] >= c0 + kFitChunk) {
+            const int32_t j = p - c0;
+            // a parent whose range leaves the chunk ends this level's climb
+            if (j < 0 || j >= m || s_link[2][j] < c0 || s_link[3][j] >= c0 + kFitChunk) {
                 frontier_push(c, &s_fcount, s_front, err);
                 break;
             }
-            const uint32_t old = __hip_atomic_fetch_add(&s_visit[p - c0], 1u, __ATOMIC_ACQ_REL,
+            const uint32_t old = __hip_atomic_fetch_add(&s_visit[j], 1u, __ATOMIC_ACQ_REL,
                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old == 0) break;
             float lo[3], hi[3];
-            const int32_t ch[2] = {left[p], right[p]};
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
+                const int32_t ch = s_link[side][j];
                 float clo[3], chi[3];
-                if (ch[side] < 0) {
-                    const float4 q = sorted[~ch[side]];
-                    clo[0] = chi[0] = q.x;
-                    clo[1] = chi[1] = q.y;
-                    clo[2] = chi[2] = q.z;
+                if (ch < 0) {
+                    const int32_t t = ~ch - c0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) clo[d] = chi[d] = s_pos[d][t];
                 } else {
-                    const int32_t j = ch[side] - c0;
+                    const int32_t t = ch - c0;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
-                        clo[d] = s_box[d][j];
-                        chi[d] = s_box[3 + d][j];
+                        clo[d] = s_box[d][t];
+                        chi[d] = s_box[3 + d][t];
                     }
                 }
 #pragma unroll
@@ -197,18 +221,17 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_local(const float4 *__restr
                     hi[d] = side ? fmaxf(hi[d], chi[d]) : chi[d];
                 }
             }
-            const int32_t j = p - c0;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 s_box[d][j] = lo[d];
                 s_box[3 + d][j] = hi[d];
             }
             c = p;
-            p = parent[p];
+            p = s_link[4][j];
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kFitChunk; i += kFitThreads) {
+    for (int i = threadIdx.x; i < m; i += kFitThreads) {
         if (s_visit[i] == 2) {
             box_lo[c0 + i] = make_float4(s_box[0][i], s_box[1][i], s_box[2][i], 0.0f);
             box_hi[c0 + i] = make_float4(s_box[3][i], s_box[4][i], s_box[5][i], 0.0f);
@@ -363,7 +386,7 @@ size_t workspace_bytes(int32_t cap) {
     size_t b = 0;
     b += 4 * al(c * 4);                       // keys, vals, keys2, vals2
     b += al(256 * tiles * 4) + al(256 * 4);   // histograms
-    b += al(c * 16);                          // sorted
+    b += al((c + kSortedPad) * 16);           // sorted (+ padding read by whole-run loads)
     b += 6 * al(c * 4);                       // left right rf rl parent leaf_parent
     b += al(c * 4);                           // visit
     b += 2 * al(c * 16);                      // boxes
@@ -395,7 +418,7 @@ void workspace_carve(Workspace &w, void *base, int32_t cap) {
     w.vals2 = (uint32_t *)take(c * 4);
     w.hist = (uint32_t *)take(256 * tiles * 4);
     w.digit_total = (uint32_t *)take(256 * 4);
-    w.sorted = (float4 *)take(c * 16);
+    w.sorted = (float4 *)take((c + kSortedPad) * 16);
     w.left = (int32_t *)take(c * 4);
     w.right = (int32_t *)take(c * 4);
     w.rf = (int32_t *)take(c * 4);

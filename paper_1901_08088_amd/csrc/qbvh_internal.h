@@ -32,6 +32,11 @@ struct TreeMeta {
 };
 static_assert(sizeof(TreeMeta) == 64, "TreeMeta is 64 bytes");
 
+// The traversal loads a leaf run of up to 8 particles as 8 consecutive
+// float4 whatever its length; the sorted array carries this many spare
+// entries after its last particle so those loads stay inside the buffer.
+constexpr int32_t kSortedPad = 8;
+
 // Device workspace of one built tree (all arrays sized for `cap` particles).
 struct Workspace {
     int32_t cap = 0;
@@ -41,7 +46,7 @@ struct Workspace {
     uint32_t *keys = nullptr, *vals = nullptr, *keys2 = nullptr, *vals2 = nullptr;
     uint32_t *hist = nullptr;       // [256][tiles]
     uint32_t *digit_total = nullptr;// [256]
-    float4 *sorted = nullptr;       // [cap]
+    float4 *sorted = nullptr;       // [cap + kSortedPad]
     int32_t *left = nullptr, *right = nullptr, *rf = nullptr, *rl = nullptr;
     int32_t *parent = nullptr, *leaf_parent = nullptr;
     uint32_t *visit = nullptr;

@@ -123,33 +123,43 @@ __device__ __forceinline__ void flush_ring(Lane &q, int32_t (*s_out)[kBlock], in
     q.flushed = f + kFlush;
 }
 
-// fp32 pass over up to 8 particles of a run for every lane.  Accepts what is
+// The candidate's original index, inverted from its float4 w word (held in a
+// scalar register) straight into a VGPR: one VALU op, no scalar op.
+__device__ __forceinline__ int32_t orig_of(float w) {
+    int32_t r;
+    asm("v_not_b32 %0, %1" : "=v"(r) : "s"(__float_as_int(w)));
+    return r;
+}
+
+// fp32 pass over the particles of a run for every lane.  Accepts what is
 // surely in (d2 <= thr; thr = r2in for hitting lanes, -1 otherwise) and
-// returns whether some lane saw a pair in the shell (thr, out] that needs the
-// exact test (out = r2out for hitting lanes, -1 otherwise).  kSelf: the run
-// may hold the lane's own particle at index `rel`, which is never listed.
+// counts in `nout` the pairs with d2 <= out (out = r2out for hitting lanes,
+// -1 otherwise); since thr <= out, some pair lies in the shell (thr, out]
+// that needs the exact test exactly when nout exceeds the accepted count.
+// The whole run (8 float4, padding included) is fetched with uniform loads
+// up front.  kSelf: the run may hold the lane's own particle at index `rel`,
+// which is never listed (nor counted in nout).
 template <bool kSelf, int kBlock>
-__device__ __forceinline__ bool run_fp32(const float4 *__restrict__ run, uint32_t count, uint32_t rel, float thr,
-                                         float out, Lane &q, int32_t (*s_out)[kBlock]) {
-    bool shell = false;
-    for (uint32_t j0 = 0; j0 < count; j0 += 4) {
-        // up to four uniform loads issued before any use
-        float4 p[4];
+__device__ __forceinline__ int32_t run_fp32(const float4 *__restrict__ run, uint32_t count, uint32_t rel,
+                                            float thr, float out, Lane &q, int32_t (*s_out)[kBlock]) {
+    float4 p[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) p[u] = (j0 + u < count) ? run[j0 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int u = 0; u < 8; ++u) p[u] = run[u];
+    // both halves of the run are requested before the first test (the
+    // compiler would otherwise delay the second load behind the early exits)
+    asm volatile("" ::"s"(p[0].x), "s"(p[4].x));
+    int32_t nout = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (j0 + u >= count) break;
-            const float ax = p[u].x - q.qsx, ay = p[u].y - q.qsy, az = p[u].z - q.qsz;
-            const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
-            bool acc = d2 <= thr;
-            shell = shell || (!acc && d2 <= out);
-            if (kSelf) acc = acc && (j0 + u != rel);
-            s_out[q.cnt & (kRing - 1)][threadIdx.x] = ~__float_as_int(p[u].w);
-            q.cnt += acc ? 1 : 0;
-        }
+    for (int u = 0; u < 8; ++u) {
+        if ((uint32_t)u >= count) break;
+        const float ax = p[u].x - q.qsx, ay = p[u].y - q.qsy, az = p[u].z - q.qsz;
+        const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
+        const bool other = !kSelf || (uint32_t)u != rel;
+        s_out[q.cnt & (kRing - 1)][threadIdx.x] = orig_of(p[u].w);
+        q.cnt += (d2 <= thr && other) ? 1 : 0;
+        nout += (d2 <= out && other) ? 1 : 0;
     }
-    return shell;
+    return nout;
 }
 
 // Decide the particles of one hit run for the lanes with `hit` set.
@@ -169,9 +179,10 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, Lane &q, int img
     const uint32_t rel = (uint32_t)(q.k - (int32_t)first);
     const float out = hit ? q.r2out : -1.0f;
     const bool self = img == 13 && __any(hit && rel < count);
-    const bool shell = self ? run_fp32<true, kBlock>(run, count, rel, thr, out, q, s_out)
-                            : run_fp32<false, kBlock>(run, count, rel, thr, out, q, s_out);
-    if (__any(shell)) {
+    const int32_t cnt0 = q.cnt;
+    const int32_t nout = self ? run_fp32<true, kBlock>(run, count, rel, thr, out, q, s_out)
+                              : run_fp32<false, kBlock>(run, count, rel, thr, out, q, s_out);
+    if (__any(nout != q.cnt - cnt0)) {
         // some pair lies in the shell around the cutoff: decide the shell
         // pairs with the definition's fp64 arithmetic
         const double sx = (double)(img % 3 - 1) * L[0];

@@ -341,7 +341,8 @@ def served_sims(n_sims: int = 64, n_slabs: int = 16, seed=SEEDS["served"], n_min
             c = slab(t, seed=sub, box=box)
             c.name = f"sim{k}_{c.name}"
         else:
-            n_i = max(200, int(round(n)))
+            # at least 400 particles, so the box edge exceeds twice the list radius
+            n_i = max(400, int(round(n)))
             c = lj_fluid(n_i, seed=sub)
             c.name = f"sim{k}_lj_N{n_i}"
         c.meta = dict(c.meta, sim=k)
