@@ -42,21 +42,21 @@ namespace qbi {
 namespace {
 
 // Decoding a 16-bit bound q of a record word held in a scalar register: the
-// float with bits 0x4B000000 | q is exactly 2^23 + q.  One VALU op per bound
-// (v_or_b32 with a 16-bit source select of the scalar word against the bias
-// held in a VGPR) keeps the decode off the scalar unit, which is the other
-// scarce issue slot of the shared walk.
+// float with bits 0x4B000000 | q is exactly 2^23 + q.  The lower bound is
+// decoded by the scalar unit (s_pack_ll_b32_b16 puts 0x4B00 above the low half
+// word), the upper one by the VALU (v_or_b32 with a 16-bit source select of
+// the scalar word against the bias held in a VGPR).  Splitting the decodes
+// balances the two issue slots of the shared walk, and leaves the clamp with
+// one scalar and one vector bound (a VALU op may read one scalar operand).
 __device__ __forceinline__ uint32_t vgpr_bias() {
     uint32_t v;
     asm volatile("v_mov_b32 %0, 0x4b000000" : "=v"(v));
     return v;
 }
 
-__device__ __forceinline__ float lo_bound(uint32_t w, uint32_t bias) {
+__device__ __forceinline__ float lo_bound(uint32_t w) {
     float r;
-    asm("v_or_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:DWORD"
-        : "=v"(r)
-        : "s"(w), "v"(bias));
+    asm("s_pack_ll_b32_b16 %0, %1, 0x4b00" : "=s"(r) : "s"(w));
     return r;
 }
 
@@ -71,9 +71,9 @@ __device__ __forceinline__ float hi_bound(uint32_t w, uint32_t bias) {
 // Squared grid-unit distance from the query (ux, uy, uz) to a packed box.
 __device__ __forceinline__ float box_d2(uint32_t wx, uint32_t wy, uint32_t wz, float ux, float uy, float uz,
                                         uint32_t bias) {
-    const float cx = __builtin_amdgcn_fmed3f(ux, lo_bound(wx, bias), hi_bound(wx, bias)) - ux;
-    const float cy = __builtin_amdgcn_fmed3f(uy, lo_bound(wy, bias), hi_bound(wy, bias)) - uy;
-    const float cz = __builtin_amdgcn_fmed3f(uz, lo_bound(wz, bias), hi_bound(wz, bias)) - uz;
+    const float cx = __builtin_amdgcn_fmed3f(ux, lo_bound(wx), hi_bound(wx, bias)) - ux;
+    const float cy = __builtin_amdgcn_fmed3f(uy, lo_bound(wy), hi_bound(wy, bias)) - uy;
+    const float cz = __builtin_amdgcn_fmed3f(uz, lo_bound(wz), hi_bound(wz, bias)) - uz;
     return __builtin_fmaf(cz, cz, __builtin_fmaf(cy, cy, cx * cx));
 }
 
@@ -162,11 +162,62 @@ __device__ __forceinline__ int32_t run_fp32(const float4 *__restrict__ run, uint
     return nout;
 }
 
+// Sparse runs.  When at most 8 lanes hit a run, testing every particle on
+// all 64 lanes wastes most of them.  Instead each lane takes one
+// (hitting lane, particle) pair: lane l takes particle l % 8 of the (l / 8)-th
+// hitting lane (lanes whose particle index reaches the run length idle).  The
+// query's image and thresholds come from its lane by a cross-lane read, the
+// particle by a vector load.  An accepted pair is written into the ring of its
+// query's lane at that lane's count plus the number of accepted pairs of the
+// same query before it, so every row receives exactly the entries, in exactly
+// the order, of the per-lane pass.  Returns whether some pair fell in the
+// shell (thr, out] (then the caller decides the shell exactly).  Never used
+// for runs that may hold a lane's own particle.  s_src is the wavefront's
+// 64-entry LDS table rank -> lane.  Every cross-lane read runs on all lanes:
+// a lane left out of one would hand its readers 0.
+template <int kBlock>
+__device__ __forceinline__ bool run_sparse(const float4 *__restrict__ run, uint32_t count, bool hit, uint64_t hits,
+                                           float thr, float out, Lane &q, int32_t (*s_out)[kBlock],
+                                           int32_t *s_src) {
+    const uint32_t lane = __lane_id();
+    const uint32_t i = lane >> 3, j = lane & 7u;
+    const uint32_t h = (uint32_t)__popcll(hits);
+    const bool pv = i < h && j < count;
+    const float4 p = run[j];  // j < 8: inside the run or its padding
+    const uint32_t rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(hits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hits, 0u));
+    if (hit) s_src[rank] = (int32_t)lane;
+    __builtin_amdgcn_wave_barrier();
+    const int32_t src = s_src[i < h ? i : 0u];
+    const float sx = __shfl(q.qsx, src), sy = __shfl(q.qsy, src), sz = __shfl(q.qsz, src);
+    const float th = __shfl(thr, src), ou = __shfl(out, src);
+    const int32_t c0 = __shfl(q.cnt, src);
+    const float ax = p.x - sx, ay = p.y - sy, az = p.z - sz;
+    const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
+    const bool acc = pv && d2 <= th;
+    const bool shell = __any(pv && !(d2 <= th) && d2 <= ou);
+    const uint64_t A = __ballot(acc);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(A >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)A, 0u));
+    const uint32_t below0 = (uint32_t)__shfl((int32_t)below, (int32_t)(lane & ~7u));
+    if (acc) {
+        const uint32_t pos = (uint32_t)c0 + below - below0;
+        s_out[pos & (kRing - 1)][(threadIdx.x & ~63u) + (uint32_t)src] = ~__float_as_int(p.w);
+    }
+    // every hitting lane adds the accepted pairs of its own 8 lanes
+    const uint32_t e0 = (rank & 7u) << 3;
+    const uint32_t b0 = (uint32_t)__shfl((int32_t)below, (int32_t)e0);
+    const uint32_t b1r = (uint32_t)__shfl((int32_t)below, (int32_t)((e0 + 8u) & 63u));
+    const uint32_t b1 = e0 + 8u < 64u ? b1r : (uint32_t)__popcll(A);
+    if (hit) q.cnt += (int32_t)(b1 - b0);
+    return shell;
+}
+
 // Decide the particles of one hit run for the lanes with `hit` set.
 template <bool kVec4, int kBlock>
 __device__ __forceinline__ void take_run(int32_t ref, bool hit, Lane &q, int img, const double (&L)[3],
                                          const float4 *__restrict__ sorted, uint32_t nend,
-                                         int32_t (*s_out)[kBlock], int32_t *nbr, int32_t max_nbr) {
+                                         int32_t (*s_out)[kBlock], int32_t *s_src, int32_t *nbr,
+                                         int32_t max_nbr) {
     const int32_t v = ~ref;
     const uint32_t first = (uint32_t)uniform(v >> 3);
     const uint32_t count = (uint32_t)uniform((v & 7) + 1);
@@ -179,10 +230,17 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, Lane &q, int img
     const uint32_t rel = (uint32_t)(q.k - (int32_t)first);
     const float out = hit ? q.r2out : -1.0f;
     const bool self = img == 13 && __any(hit && rel < count);
-    const int32_t cnt0 = q.cnt;
-    const int32_t nout = self ? run_fp32<true, kBlock>(run, count, rel, thr, out, q, s_out)
-                              : run_fp32<false, kBlock>(run, count, rel, thr, out, q, s_out);
-    if (__any(nout != q.cnt - cnt0)) {
+    const uint64_t hits = __ballot(hit);
+    bool shell;
+    if (!self && __popcll(hits) <= 8) {
+        shell = run_sparse<kBlock>(run, count, hit, hits, thr, out, q, s_out, s_src);
+    } else {
+        const int32_t cnt0 = q.cnt;
+        const int32_t nout = self ? run_fp32<true, kBlock>(run, count, rel, thr, out, q, s_out)
+                                  : run_fp32<false, kBlock>(run, count, rel, thr, out, q, s_out);
+        shell = __any(nout != q.cnt - cnt0);
+    }
+    if (shell) {
         // some pair lies in the shell around the cutoff: decide the shell
         // pairs with the definition's fp64 arithmetic
         const double sx = (double)(img % 3 - 1) * L[0];
@@ -212,7 +270,8 @@ template <bool kVec4, int kBlock>
 __device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local, const uint4 *__restrict__ records,
                                                const int32_t *__restrict__ ropes,
                                                const float4 *__restrict__ sorted,
-                                               const TreeMeta *__restrict__ meta, int32_t (*s_out)[kBlock]);
+                                               const TreeMeta *__restrict__ meta, int32_t (*s_out)[kBlock],
+                                               int32_t (*s_src)[64]);
 
 // Workgroups are dealt round-robin to the 8 XCDs; each XCD gets one
 // contiguous stretch of the Z-ordered queries so its L2 holds one region.
@@ -227,7 +286,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     TravArgs a, const uint4 *__restrict__ records, const int32_t *__restrict__ ropes,
     const float4 *__restrict__ sorted, const TreeMeta *__restrict__ meta) {
     __shared__ int32_t s_out[kRing][kBlock];
-    traverse_block<kVec4, kBlock>(a, xcd_logical_block(), records, ropes, sorted, meta, s_out);
+    __shared__ int32_t s_src[kBlock / 64][64];
+    traverse_block<kVec4, kBlock>(a, xcd_logical_block(), records, ropes, sorted, meta, s_out, s_src);
 }
 
 // Batched form: the workgroups of all systems form one grid; each workgroup
@@ -240,10 +300,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const uint4 *__restrict__ records, const int32_t *__restrict__ ropes, const float4 *__restrict__ sorted,
     const TreeMeta *__restrict__ meta_all) {
     __shared__ int32_t s_out[kRing][kBlock];
+    __shared__ int32_t s_src[kBlock / 64][64];
     const int32_t logical = xcd_logical_block();
     const int32_t sys = find_seg(tblk_first, nsys, logical);
     traverse_block<kVec4, kBlock>(table[sys], logical - tblk_first[sys], records, ropes, sorted,
-                                  meta_all + sys * QBVH_MAX_TYPES, s_out);
+                                  meta_all + sys * QBVH_MAX_TYPES, s_out, s_src);
 }
 
 // One workgroup of queries: local workgroup `local` of the system `a`.
@@ -251,7 +312,9 @@ template <bool kVec4, int kBlock>
 __device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local, const uint4 *__restrict__ records,
                                                const int32_t *__restrict__ ropes,
                                                const float4 *__restrict__ sorted,
-                                               const TreeMeta *__restrict__ meta, int32_t (*s_out)[kBlock]) {
+                                               const TreeMeta *__restrict__ meta, int32_t (*s_out)[kBlock],
+                                               int32_t (*s_src_all)[64]) {
+    int32_t *s_src = s_src_all[threadIdx.x >> 6];
     const int32_t li = local * kBlock + (int32_t)threadIdx.x;
     const bool valid = li < a.n;  // idle lanes still take part in the shared walk
     const int32_t k = a.start + li;
@@ -337,7 +400,7 @@ __device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local,
             q.uy = (float)((((double)q.y + sy) - (double)m.lo[1]) * m.inv_h + 8388608.0);
             q.uz = (float)((((double)q.z + sz) - (double)m.lo[2]) * m.inv_h + 8388608.0);
             if (root < 0) {  // a tree of at most leaf_size particles is one run
-                take_run<kVec4, kBlock>(root, on, q, img, a.L, sorted, nend, s_out, a.nbr, a.max_nbr);
+                take_run<kVec4, kBlock>(root, on, q, img, a.L, sorted, nend, s_out, s_src, a.nbr, a.max_nbr);
                 continue;
             }
             int32_t v = root;
@@ -350,9 +413,9 @@ __device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local,
                 const bool anyl = __any(hl), anyr = __any(hr);
                 const int32_t cl = (int32_t)r1.z, cr = (int32_t)r1.w;
                 if (cl < 0 && anyl)
-                    take_run<kVec4, kBlock>(cl, hl, q, img, a.L, sorted, nend, s_out, a.nbr, a.max_nbr);
+                    take_run<kVec4, kBlock>(cl, hl, q, img, a.L, sorted, nend, s_out, s_src, a.nbr, a.max_nbr);
                 if (cr < 0 && anyr)
-                    take_run<kVec4, kBlock>(cr, hr, q, img, a.L, sorted, nend, s_out, a.nbr, a.max_nbr);
+                    take_run<kVec4, kBlock>(cr, hr, q, img, a.L, sorted, nend, s_out, s_src, a.nbr, a.max_nbr);
                 const int32_t next = (anyl && cl >= 0) ? cl : ((anyr && cr >= 0) ? cr : rope);
                 // references always point forward; max() makes progress unconditional
                 v = uniform(max(next, v + 1));
