@@ -136,6 +136,30 @@ QBVH_API int qbvh_build(qbvh_t **tree, const float *d_pos, const int32_t *d_type
 QBVH_API int nlist_build(const qbvh_t *tree, const float *rcut, float skin, int32_t max_nbr,
                 int32_t *d_nbr, int32_t *d_count, int32_t *d_overflow, qbvh_stream_t stream);
 
+/* List semantics of nlist_build_ex. */
+enum {
+    QBVH_LIST_EXACT = 0, /* the exact list defined at the top (what nlist_build writes) */
+    QBVH_LIST_PAPER = 1  /* the paper's lists (Section 2.3): j is listed for i when i's
+                            sphere (radius rcut[t_i][t_j] + skin, any periodic image)
+                            overlaps j's cell box -- j's position snapped outward to the
+                            grid of its type's tree (Section 2.2), the leaf box of a
+                            one-particle leaf -- with no distance check.  A superset of
+                            the exact list; the extra entries are the paper's false
+                            positives (about rho (3 pi h R^2 + 6 h^2 R + h^3) per
+                            particle for bin width h).  The test uses the radius
+                            R/h (1 + 2^-20) + 0.02 in grid units, which covers its
+                            rounding; the relation is not symmetric. */
+};
+
+/*
+ * nlist_build_ex -- nlist_build with a choice of list semantics (`mode`, one
+ * of QBVH_LIST_*; anything else is QBVH_EINVAL).  Paper mode first writes
+ * every particle's cell box into the tree's workspace (stream-ordered).
+ * Arguments, layouts and outputs otherwise as nlist_build.
+ */
+QBVH_API int nlist_build_ex(const qbvh_t *tree, const float *rcut, float skin, int32_t max_nbr, int32_t mode,
+                   int32_t *d_nbr, int32_t *d_count, int32_t *d_overflow, qbvh_stream_t stream);
+
 /* One independent system of a batch. */
 typedef struct {
     const float *d_pos;    /* device float [n][3] */

@@ -22,7 +22,7 @@ OK, EINVAL, EGEOM, ENOMEM, EHIP, EAGAIN, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 EXPORT = dict(keys=1, perm=2, sorted=3, left=4, right=5, range_f=6, range_l=7, parent=8,
               leaf_parent=9, box_lo=10, box_hi=11, records=12, ropes=13)
 
-C_API = ("qbvh_build", "nlist_build", "nlist_build_many", "nlist_batch_stats", "nlist_batch_release",
+C_API = ("qbvh_build", "nlist_build", "nlist_build_ex", "nlist_build_many", "nlist_batch_stats", "nlist_batch_release",
          "qbvh_server_create", "qbvh_server_submit", "qbvh_server_poll", "qbvh_server_wait",
          "qbvh_server_result", "qbvh_server_stats", "qbvh_server_destroy",
          "qbvh_free", "qbvh_strerror", "qbvh_last_hip_error", "qbvh_workspace_bytes", "qbvh_info",
@@ -108,6 +108,8 @@ def lib():
             L.qbvh_build.restype = ctypes.c_int
             L.nlist_build.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_float, I32, P, P, P, P]
             L.nlist_build.restype = ctypes.c_int
+            L.nlist_build_ex.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_float, I32, I32, P, P, P, P]
+            L.nlist_build_ex.restype = ctypes.c_int
             L.nlist_build_many.argtypes = [I32, ctypes.POINTER(QbvhSystem), ctypes.POINTER(QbvhBatchOpts), P]
             L.nlist_build_many.restype = ctypes.c_int
             L.nlist_batch_stats.argtypes = [P, ctypes.POINTER(QbvhBatchStats)]
@@ -233,6 +235,22 @@ def nlist_build(tree: Tree, rcut, skin: float, max_nbr: int, nbr, count, overflo
                             _stream(stream))
     del rc
     _check(rc_, "nlist_build")
+
+
+LIST_EXACT, LIST_PAPER = 0, 1
+
+
+def nlist_build_ex(tree: Tree, rcut, skin: float, max_nbr: int, mode: int, nbr, count, overflow,
+                   stream=None) -> None:
+    """nlist_build with a list semantics: LIST_EXACT or LIST_PAPER (leaf-box overlap lists)."""
+    import torch
+    rc, rp = _rcut_array(rcut, tree.ntypes)
+    rc_ = lib().nlist_build_ex(tree.ptr, rp, float(skin), int(max_nbr), int(mode),
+                               _dev_ptr(nbr, torch.int32, "nbr", allow_none=True),
+                               _dev_ptr(count, torch.int32, "count"), _dev_ptr(overflow, torch.int32, "overflow"),
+                               _stream(stream))
+    del rc
+    _check(rc_, "nlist_build_ex")
 
 
 def nlist_build_many(systems, opts=None, stream=None) -> None:

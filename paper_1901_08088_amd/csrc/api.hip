@@ -181,9 +181,10 @@ int qbvh_build(qbvh_t **tree, const float *d_pos, const int32_t *d_type, int32_t
     return QBVH_OK;
 }
 
-int nlist_build(const qbvh_t *tree, const float *rcut, float skin, int32_t max_nbr, int32_t *d_nbr,
-                int32_t *d_count, int32_t *d_overflow, qbvh_stream_t stream) {
+int nlist_build_ex(const qbvh_t *tree, const float *rcut, float skin, int32_t max_nbr, int32_t mode,
+                   int32_t *d_nbr, int32_t *d_count, int32_t *d_overflow, qbvh_stream_t stream) {
     if (!tree || max_nbr < 0 || !d_overflow) return QBVH_EINVAL;
+    if (mode != QBVH_LIST_EXACT && mode != QBVH_LIST_PAPER) return QBVH_EINVAL;
     if (tree->n > 0 && (!d_count || (max_nbr > 0 && !d_nbr))) return QBVH_EINVAL;
     qbi::TravArgs a{};
     int rc = list_radii(rcut, skin, tree->ntypes, tree->box, a.rlist2);
@@ -200,9 +201,18 @@ int nlist_build(const qbvh_t *tree, const float *rcut, float skin, int32_t max_n
     a.ntypes = tree->ntypes;
     a.max_nbr = max_nbr;
     const bool vec4 = max_nbr > 0 && (max_nbr % 4) == 0 && (((uintptr_t)d_nbr) & 15u) == 0;
-    hipError_t e = qbi::launch_traverse(a, tree->opts.block_size, vec4, (hipStream_t)stream);
+    const bool paper = mode == QBVH_LIST_PAPER;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (paper) e = qbi::launch_qpoint(tree->ws, tree->n, tree->ntypes, tree->opts.qbits, s);
+    if (e == hipSuccess) e = qbi::launch_traverse(a, tree->opts.block_size, vec4, paper, tree->ws.qpoint, s);
     if (e != hipSuccess) return hip_fail(e);
     return QBVH_OK;
+}
+
+int nlist_build(const qbvh_t *tree, const float *rcut, float skin, int32_t max_nbr, int32_t *d_nbr,
+                int32_t *d_count, int32_t *d_overflow, qbvh_stream_t stream) {
+    return nlist_build_ex(tree, rcut, skin, max_nbr, QBVH_LIST_EXACT, d_nbr, d_count, d_overflow, stream);
 }
 
 int qbvh_info(const qbvh_t *tree, qbvh_info_t *info) {

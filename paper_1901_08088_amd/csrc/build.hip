@@ -354,6 +354,24 @@ __global__ __launch_bounds__(kBuildThreads) void k_emit(int32_t n, int32_t ntype
     emit_record(i, f, l, m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, qbits, records, ropes);
 }
 
+// Cell box of every sorted particle in its type tree's grid (the leaf box of a
+// one-particle leaf, Section 2.2), packed like a record box, plus its original
+// index: what paper-mode lists test (Section 2.3).
+__global__ __launch_bounds__(kBuildThreads) void k_qpoint(int32_t n, int32_t ntypes, const float4 *__restrict__ sorted,
+                                                          const TreeMeta *__restrict__ meta, int32_t qbits,
+                                                          uint4 *__restrict__ qpoint) {
+    const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
+    if (k >= n) return;
+    int t = 0;
+    for (int u = 1; u < ntypes; ++u)
+        if (k >= meta[u].start && meta[u].count > 0) t = u;
+    const TreeMeta &m = meta[t];
+    const uint32_t qmax = (1u << qbits) - 1u;
+    const float4 p = sorted[k];
+    qpoint[k] = make_uint4(quantize_axis(p.x, p.x, m.lo[0], m.h, qmax), quantize_axis(p.y, p.y, m.lo[1], m.h, qmax),
+                           quantize_axis(p.z, p.z, m.lo[2], m.h, qmax), (uint32_t)~__float_as_int(p.w));
+}
+
 inline dim3 grid_for(int64_t items) { return dim3((unsigned)((items + kBuildThreads - 1) / kBuildThreads)); }
 
 }  // namespace
@@ -378,6 +396,13 @@ hipError_t launch_fit(const Workspace &w, int32_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_qpoint(const Workspace &w, int32_t n, int32_t ntypes, int32_t qbits, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_qpoint, grid_for(n), dim3(kBuildThreads), 0, s, n, ntypes, w.sorted, w.meta, qbits,
+                           w.qpoint);
+    return hipGetLastError();
+}
+
 size_t workspace_bytes(int32_t cap) {
     const size_t c = cap > 0 ? (size_t)cap : 1;
     const size_t tiles = (size_t)radix_tiles((int32_t)c);
@@ -392,6 +417,7 @@ size_t workspace_bytes(int32_t cap) {
     b += 2 * al(c * 16);                      // boxes
     b += al((c + 1) * 4) + al(sb * 4);        // kept + scan partials
     b += al(c * 32) + al(c * 4);              // records + ropes
+    b += al((c + kSortedPad) * 16);           // cell boxes (paper-mode lists)
     b += al(QBVH_MAX_TYPES * sizeof(TreeMeta)) + al(QBVH_MAX_TYPES * 4) + al(4);
     const size_t nf = (size_t)fit_chunks0((int32_t)c);
     b += 2 * (al(nf * kFrontierCap * 4) + al(nf * 4));  // fit frontiers (ping-pong)
@@ -431,6 +457,7 @@ void workspace_carve(Workspace &w, void *base, int32_t cap) {
     w.kept = (uint32_t *)take((c + 1) * 4);
     w.scan_part = (uint32_t *)take(sb * 4);
     w.records = (uint4 *)take(c * 32);
+    w.qpoint = (uint4 *)take((c + kSortedPad) * 16);
     w.ropes = (int32_t *)take(c * 4);
     w.meta = (TreeMeta *)take(QBVH_MAX_TYPES * sizeof(TreeMeta));
     w.type_count = (uint32_t *)take(QBVH_MAX_TYPES * 4);

@@ -54,6 +54,9 @@ struct Workspace {
     uint32_t *kept = nullptr;       // [cap + 1]: kept-node counts, scanned in place
     uint32_t *scan_part = nullptr;  // [scan blocks + 1]
     uint4 *records = nullptr;       // [cap][2]: two-wide quantized records
+    uint4 *qpoint = nullptr;        // [cap + kSortedPad]: per sorted particle, its quantized cell box
+                                    // (words 0-2 as a record box) and original index (word 3);
+                                    // written only for paper-mode lists
     int32_t *ropes = nullptr;       // [cap]
     TreeMeta *meta = nullptr;       // [QBVH_MAX_TYPES]
     uint32_t *type_count = nullptr; // [QBVH_MAX_TYPES]
@@ -131,7 +134,9 @@ void fill_trav_box(TravArgs &a, const float box[3]);
 hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d_type, int32_t n,
                         int32_t ntypes, const float box[3], int32_t leaf_size, int32_t qbits,
                         int32_t validate, hipStream_t s);
-hipError_t launch_traverse(const TravArgs &a, int32_t block, bool vec4, hipStream_t s);
+hipError_t launch_traverse(const TravArgs &a, int32_t block, bool vec4, bool paper, const uint4 *qpoint,
+                           hipStream_t s);
+hipError_t launch_qpoint(const Workspace &w, int32_t n, int32_t ntypes, int32_t qbits, hipStream_t s);
 hipError_t launch_traverse_batch(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,

@@ -100,6 +100,8 @@ struct Lane {
     int32_t k, orig;
     int32_t cnt;           // entries of the list so far
     int32_t flushed;       // entries already written to the row (a multiple of kFlush)
+    float px, py, pz;      // paper mode: query image in grid units (plain, not offset)
+    float rp2;             // paper mode: squared tight radius in grid units
 };
 
 template <bool kVec4, int kBlock>
@@ -212,11 +214,49 @@ __device__ __forceinline__ bool run_sparse(const float4 *__restrict__ run, uint3
     return shell;
 }
 
+// 16-bit bound of a record-style word held in a scalar register, as a float.
+__device__ __forceinline__ float cvt_lo(uint32_t w) {
+    float r;
+    asm("v_cvt_f32_u32_sdwa %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0" : "=v"(r) : "s"(w));
+    return r;
+}
+
+__device__ __forceinline__ float cvt_hi(uint32_t w) {
+    float r;
+    asm("v_cvt_f32_u32_sdwa %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1" : "=v"(r) : "s"(w));
+    return r;
+}
+
+// Paper-mode pass (Section 2.3): a particle of the run is listed when the
+// lane's sphere overlaps the particle's own cell box (its leaf box in the
+// quantized tree), with no distance check.  The test runs in plain grid units
+// against the tight radius (R/h)(1 + 2^-20) + 0.02.
+template <bool kSelf, int kBlock>
+__device__ __forceinline__ void run_paper(const uint4 *__restrict__ qrun, uint32_t count, uint32_t rel, bool hit,
+                                          Lane &q, int32_t (*s_out)[kBlock]) {
+    uint4 b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b[u] = qrun[u];
+    asm volatile("" ::"s"(b[0].x), "s"(b[4].x));
+    const float r2 = hit ? q.rp2 : -1.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        if ((uint32_t)u >= count) break;
+        const float cx = __builtin_amdgcn_fmed3f(q.px, cvt_lo(b[u].x), cvt_hi(b[u].x)) - q.px;
+        const float cy = __builtin_amdgcn_fmed3f(q.py, cvt_lo(b[u].y), cvt_hi(b[u].y)) - q.py;
+        const float cz = __builtin_amdgcn_fmed3f(q.pz, cvt_lo(b[u].z), cvt_hi(b[u].z)) - q.pz;
+        const float d2 = __builtin_fmaf(cz, cz, __builtin_fmaf(cy, cy, cx * cx));
+        const bool other = !kSelf || (uint32_t)u != rel;
+        s_out[q.cnt & (kRing - 1)][threadIdx.x] = (int32_t)b[u].w;
+        q.cnt += (d2 <= r2 && other) ? 1 : 0;
+    }
+}
+
 // Decide the particles of one hit run for the lanes with `hit` set.
-template <bool kVec4, int kBlock>
+template <bool kVec4, int kBlock, bool kPaper>
 __device__ __forceinline__ void take_run(int32_t ref, bool hit, Lane &q, int img, const double (&L)[3],
-                                         const float4 *__restrict__ sorted, uint32_t nend,
-                                         int32_t (*s_out)[kBlock], int32_t *s_src, int32_t *nbr,
+                                         const float4 *__restrict__ sorted, const uint4 *__restrict__ qpoint,
+                                         uint32_t nend, int32_t (*s_out)[kBlock], int32_t *s_src, int32_t *nbr,
                                          int32_t max_nbr) {
     const int32_t v = ~ref;
     const uint32_t first = (uint32_t)uniform(v >> 3);
@@ -230,6 +270,15 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, Lane &q, int img
     const uint32_t rel = (uint32_t)(q.k - (int32_t)first);
     const float out = hit ? q.r2out : -1.0f;
     const bool self = img == 13 && __any(hit && rel < count);
+    if (kPaper) {
+        if (self)
+            run_paper<true, kBlock>(qpoint + first, count, rel, hit, q, s_out);
+        else
+            run_paper<false, kBlock>(qpoint + first, count, rel, hit, q, s_out);
+        if (__any(q.cnt - q.flushed >= kFlush) && q.cnt - q.flushed >= kFlush)
+            flush_ring<kVec4, kBlock>(q, s_out, nbr, max_nbr);
+        return;
+    }
     const uint64_t hits = __ballot(hit);
     bool shell;
     if (!self && __popcll(hits) <= 8) {
@@ -266,10 +315,11 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, Lane &q, int img
 
 // The read-only arrays come as separate __restrict__ parameters: that lets the
 // compiler fetch wave-uniform records and particles with scalar loads.
-template <bool kVec4, int kBlock>
+template <bool kVec4, int kBlock, bool kPaper>
 __device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local, const uint4 *__restrict__ records,
                                                const int32_t *__restrict__ ropes,
                                                const float4 *__restrict__ sorted,
+                                               const uint4 *__restrict__ qpoint,
                                                const TreeMeta *__restrict__ meta, int32_t (*s_out)[kBlock],
                                                int32_t (*s_src)[64]);
 
@@ -281,13 +331,14 @@ __device__ __forceinline__ int32_t xcd_logical_block() {
     return (int32_t)(xcd * qq + (xcd < rr ? xcd : rr) + (b >> 3));
 }
 
-template <bool kVec4, int kBlock>
+template <bool kVec4, int kBlock, bool kPaper>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_traverse(
     TravArgs a, const uint4 *__restrict__ records, const int32_t *__restrict__ ropes,
-    const float4 *__restrict__ sorted, const TreeMeta *__restrict__ meta) {
+    const float4 *__restrict__ sorted, const uint4 *__restrict__ qpoint, const TreeMeta *__restrict__ meta) {
     __shared__ int32_t s_out[kRing][kBlock];
     __shared__ int32_t s_src[kBlock / 64][64];
-    traverse_block<kVec4, kBlock>(a, xcd_logical_block(), records, ropes, sorted, meta, s_out, s_src);
+    traverse_block<kVec4, kBlock, kPaper>(a, xcd_logical_block(), records, ropes, sorted, qpoint, meta, s_out,
+                                          s_src);
 }
 
 // Batched form: the workgroups of all systems form one grid; each workgroup
@@ -303,15 +354,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     __shared__ int32_t s_src[kBlock / 64][64];
     const int32_t logical = xcd_logical_block();
     const int32_t sys = find_seg(tblk_first, nsys, logical);
-    traverse_block<kVec4, kBlock>(table[sys], logical - tblk_first[sys], records, ropes, sorted,
-                                  meta_all + sys * QBVH_MAX_TYPES, s_out, s_src);
+    traverse_block<kVec4, kBlock, false>(table[sys], logical - tblk_first[sys], records, ropes, sorted, nullptr,
+                                         meta_all + sys * QBVH_MAX_TYPES, s_out, s_src);
 }
 
 // One workgroup of queries: local workgroup `local` of the system `a`.
-template <bool kVec4, int kBlock>
+template <bool kVec4, int kBlock, bool kPaper>
 __device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local, const uint4 *__restrict__ records,
                                                const int32_t *__restrict__ ropes,
                                                const float4 *__restrict__ sorted,
+                                               const uint4 *__restrict__ qpoint,
                                                const TreeMeta *__restrict__ meta, int32_t (*s_out)[kBlock],
                                                int32_t (*s_src_all)[64]) {
     int32_t *s_src = s_src_all[threadIdx.x >> 6];
@@ -383,6 +435,12 @@ __device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local,
         q.r2in = (float)(rin * rin * (1.0 - 0x1p-20));
         q.r2out = (float)(rout * rout * (1.0 + 0x1p-20));
         const int32_t root = m.root, end = m.end;
+        if (kPaper) {
+            // covers the rounding of the query's grid position (at most
+            // 2^-24 of 65535 bins) and of the fp32 distance
+            const double rp = rg * (1.0 + 0x1p-20) + 0.02;
+            q.rp2 = (float)(rp * rp * (1.0 + 0x1p-20));
+        }
 
         // (2) one shared stackless walk per image in the union (Algorithm 1, lines 5-19)
         while (wave_bits) {
@@ -399,8 +457,14 @@ __device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local,
             q.ux = (float)((((double)q.x + sx) - (double)m.lo[0]) * m.inv_h + 8388608.0);
             q.uy = (float)((((double)q.y + sy) - (double)m.lo[1]) * m.inv_h + 8388608.0);
             q.uz = (float)((((double)q.z + sz) - (double)m.lo[2]) * m.inv_h + 8388608.0);
+            if (kPaper) {
+                q.px = (float)((((double)q.x + sx) - (double)m.lo[0]) * m.inv_h);
+                q.py = (float)((((double)q.y + sy) - (double)m.lo[1]) * m.inv_h);
+                q.pz = (float)((((double)q.z + sz) - (double)m.lo[2]) * m.inv_h);
+            }
             if (root < 0) {  // a tree of at most leaf_size particles is one run
-                take_run<kVec4, kBlock>(root, on, q, img, a.L, sorted, nend, s_out, s_src, a.nbr, a.max_nbr);
+                take_run<kVec4, kBlock, kPaper>(root, on, q, img, a.L, sorted, qpoint, nend, s_out, s_src, a.nbr,
+                                                 a.max_nbr);
                 continue;
             }
             int32_t v = root;
@@ -413,9 +477,11 @@ __device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local,
                 const bool anyl = __any(hl), anyr = __any(hr);
                 const int32_t cl = (int32_t)r1.z, cr = (int32_t)r1.w;
                 if (cl < 0 && anyl)
-                    take_run<kVec4, kBlock>(cl, hl, q, img, a.L, sorted, nend, s_out, s_src, a.nbr, a.max_nbr);
+                    take_run<kVec4, kBlock, kPaper>(cl, hl, q, img, a.L, sorted, qpoint, nend, s_out, s_src, a.nbr,
+                                                    a.max_nbr);
                 if (cr < 0 && anyr)
-                    take_run<kVec4, kBlock>(cr, hr, q, img, a.L, sorted, nend, s_out, s_src, a.nbr, a.max_nbr);
+                    take_run<kVec4, kBlock, kPaper>(cr, hr, q, img, a.L, sorted, qpoint, nend, s_out, s_src, a.nbr,
+                                                    a.max_nbr);
                 const int32_t next = (anyl && cl >= 0) ? cl : ((anyr && cr >= 0) ? cr : rope);
                 // references always point forward; max() makes progress unconditional
                 v = uniform(max(next, v + 1));
@@ -437,11 +503,11 @@ __global__ void k_clear_flag(int32_t *f) {
     if (threadIdx.x == 0) *f = 0;
 }
 
-template <bool kVec4, int kBlock>
-void launch_one(const TravArgs &a, hipStream_t s) {
+template <bool kVec4, int kBlock, bool kPaper>
+void launch_one(const TravArgs &a, const uint4 *qpoint, hipStream_t s) {
     const unsigned grid = (unsigned)((a.n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_traverse<kVec4, kBlock>), dim3(grid), dim3(kBlock), 0, s, a, a.records, a.ropes, a.sorted,
-                       a.meta);
+    hipLaunchKernelGGL((k_traverse<kVec4, kBlock, kPaper>), dim3(grid), dim3(kBlock), 0, s, a, a.records, a.ropes,
+                       a.sorted, qpoint, a.meta);
 }
 
 template <bool kVec4, int kBlock>
@@ -450,13 +516,13 @@ void launch_one_batch(const BatchLaunch &b, hipStream_t s) {
                        b.tblk_first, b.nsys, b.ws.records, b.ws.ropes, b.ws.sorted, b.meta);
 }
 
-template <bool kVec4>
-void launch_block(const TravArgs &a, int32_t block, hipStream_t s) {
+template <bool kVec4, bool kPaper>
+void launch_block(const TravArgs &a, int32_t block, const uint4 *qpoint, hipStream_t s) {
     switch (block) {
-    case 64: launch_one<kVec4, 64>(a, s); break;
-    case 128: launch_one<kVec4, 128>(a, s); break;
-    case 192: launch_one<kVec4, 192>(a, s); break;
-    default: launch_one<kVec4, 256>(a, s); break;
+    case 64: launch_one<kVec4, 64, kPaper>(a, qpoint, s); break;
+    case 128: launch_one<kVec4, 128, kPaper>(a, qpoint, s); break;
+    case 192: launch_one<kVec4, 192, kPaper>(a, qpoint, s); break;
+    default: launch_one<kVec4, 256, kPaper>(a, qpoint, s); break;
     }
 }
 
@@ -472,13 +538,21 @@ void launch_block_batch(const BatchLaunch &b, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_traverse(const TravArgs &a, int32_t block, bool vec4, hipStream_t s) {
+hipError_t launch_traverse(const TravArgs &a, int32_t block, bool vec4, bool paper, const uint4 *qpoint,
+                           hipStream_t s) {
     hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, s, a.overflow);
     if (a.n > 0) {
-        if (vec4)
-            launch_block<true>(a, block, s);
-        else
-            launch_block<false>(a, block, s);
+        if (paper) {
+            if (vec4)
+                launch_block<true, true>(a, block, qpoint, s);
+            else
+                launch_block<false, true>(a, block, qpoint, s);
+        } else {
+            if (vec4)
+                launch_block<true, false>(a, block, nullptr, s);
+            else
+                launch_block<false, false>(a, block, nullptr, s);
+        }
     }
     return hipGetLastError();
 }
