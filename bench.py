@@ -90,6 +90,41 @@ def copy_probe(mib: int) -> None:
     log(f"copy probe: {mib} MiB read + {mib} MiB written per launch, 3 launches")
 
 
+def paper_mode(cfg, pos, steps: int) -> dict:
+    """Exact vs paper-mode lists (Section 2.3: leaf-box overlap, no distance
+    check) on the same workload with the paper's 10-bit grid: traversal time
+    of each and the paper mode's extra entries per particle."""
+    import torch
+    import paper_1901_08088_amd as Q
+    opts = dict(BENCH_OPTS, qbits=10)
+    tree = Q.qbvh_build(pos, None, cfg.box, 1, opts)
+    n = cfg.n
+    nbr = torch.empty((n, 320), dtype=torch.int32, device="cuda")
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    ovf = torch.empty(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {"workload": "same configuration, 10-bit grid, leaf 8, max_nbr 320"}
+    for name, mode in (("exact", Q.LIST_EXACT), ("paper", Q.LIST_PAPER)):
+        for _ in range(2):
+            Q.nlist_build_ex(tree, cfg.rcut, cfg.skin, 320, mode, nbr, cnt, ovf)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(steps):
+            Q.nlist_build_ex(tree, cfg.rcut, cfg.skin, 320, mode, nbr, cnt, ovf)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        out[f"{name}_traverse_ms"] = ev[0].elapsed_time(ev[1]) / steps
+        out[f"{name}_pairs"] = int(cnt.sum())
+        out[f"{name}_overflow"] = int(ovf.item())
+    out["false_positives_per_particle"] = (out["paper_pairs"] - out["exact_pairs"]) / n
+    Q.qbvh_free(tree)
+    del nbr
+    torch.cuda.empty_cache()
+    log(f"paper mode: {out}")
+    return out
+
+
 def batched_vs_plain(steps: int) -> dict:
     """The 256-replica ensemble (N log-uniform in [2000, 200000], density
     0.3-0.9, rc 2.5-3.0, skin 0.4, max_nbr 256): one nlist_build_many call
@@ -276,6 +311,8 @@ def main(argv=None) -> int:
     ap.add_argument("--block-size", type=int, default=BENCH_OPTS["block_size"])
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="oracle rows timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--paper-steps", type=int, default=10,
+                    help="traversals timed for the exact-vs-paper-mode comparison (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=20,
                     help="passes timed for the batched-vs-plain ensemble comparison (0 = skip)")
     ap.add_argument("--served-seconds", type=float, default=5.0,
@@ -347,6 +384,11 @@ def main(argv=None) -> int:
     if args.copy_probe_mib > 0:
         copy_probe(args.copy_probe_mib)
 
+    paper = None
+    if args.paper_steps > 0:
+        log("paper-mode lists (10-bit grid)")
+        paper = paper_mode(cfg, pos, args.paper_steps)
+
     batched = None
     if args.batched_steps > 0:
         log("batched vs plain (ensemble)")
@@ -391,6 +433,7 @@ def main(argv=None) -> int:
                      "traffic": measured_traffic(args.workload, opts),
                      "algorithmic_bytes": tbytes, "kernel_sources": kernel_source_hash()},
         "cpu_baseline": base,
+        "paper_mode": paper,
         "batched": batched,
         "served": serve,
     }

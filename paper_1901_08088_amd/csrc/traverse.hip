@@ -254,7 +254,7 @@ __device__ __forceinline__ void run_paper(const uint4 *__restrict__ qrun, uint32
 
 // Decide the particles of one hit run for the lanes with `hit` set.
 template <bool kVec4, int kBlock, bool kPaper>
-__device__ __forceinline__ void take_run(int32_t ref, bool hit, Lane &q, int img, const double (&L)[3],
+__device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, Lane &q, int img, const double (&L)[3],
                                          const float4 *__restrict__ sorted, const uint4 *__restrict__ qpoint,
                                          uint32_t nend, int32_t (*s_out)[kBlock], int32_t *s_src, int32_t *nbr,
                                          int32_t max_nbr) {
@@ -279,9 +279,9 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, Lane &q, int img
             flush_ring<kVec4, kBlock>(q, s_out, nbr, max_nbr);
         return;
     }
-    const uint64_t hits = __ballot(hit);
     bool shell;
-    if (!self && __popcll(hits) <= 8) {
+    // (two 32-bit counts keep the comparison on the scalar unit)
+    if (!self && __popc((uint32_t)hits) + __popc((uint32_t)(hits >> 32)) <= 8) {
         shell = run_sparse<kBlock>(run, count, hit, hits, thr, out, q, s_out, s_src);
     } else {
         const int32_t cnt0 = q.cnt;
@@ -463,25 +463,29 @@ __device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local,
                 q.pz = (float)((((double)q.z + sz) - (double)m.lo[2]) * m.inv_h);
             }
             if (root < 0) {  // a tree of at most leaf_size particles is one run
-                take_run<kVec4, kBlock, kPaper>(root, on, q, img, a.L, sorted, qpoint, nend, s_out, s_src, a.nbr,
-                                                 a.max_nbr);
+                take_run<kVec4, kBlock, kPaper>(root, on, __ballot(on), q, img, a.L, sorted, qpoint, nend, s_out,
+                                                s_src, a.nbr, a.max_nbr);
                 continue;
             }
             int32_t v = root;
             while (v < end) {
-                const uint4 r0 = records[2 * (uint32_t)v];
-                const uint4 r1 = records[2 * (uint32_t)v + 1];
-                const int32_t rope = ropes[(uint32_t)v];
+                // 32-bit byte offsets keep the address arithmetic to one scalar op
+                const uint32_t off = (uint32_t)v << 5;
+                const uint4 r0 = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(records) + off);
+                const uint4 r1 = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(records) + off + 16u);
+                const int32_t rope =
+                    *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(ropes) + ((uint32_t)v << 2));
                 const bool hl = box_d2(r0.x, r0.y, r0.z, q.ux, q.uy, q.uz, bias) <= q.r2g;
                 const bool hr = box_d2(r0.w, r1.x, r1.y, q.ux, q.uy, q.uz, bias) <= q.r2g;
-                const bool anyl = __any(hl), anyr = __any(hr);
+                const uint64_t ml = __ballot(hl), mr = __ballot(hr);
+                const bool anyl = ml != 0, anyr = mr != 0;
                 const int32_t cl = (int32_t)r1.z, cr = (int32_t)r1.w;
                 if (cl < 0 && anyl)
-                    take_run<kVec4, kBlock, kPaper>(cl, hl, q, img, a.L, sorted, qpoint, nend, s_out, s_src, a.nbr,
-                                                    a.max_nbr);
+                    take_run<kVec4, kBlock, kPaper>(cl, hl, ml, q, img, a.L, sorted, qpoint, nend, s_out, s_src,
+                                                    a.nbr, a.max_nbr);
                 if (cr < 0 && anyr)
-                    take_run<kVec4, kBlock, kPaper>(cr, hr, q, img, a.L, sorted, qpoint, nend, s_out, s_src, a.nbr,
-                                                    a.max_nbr);
+                    take_run<kVec4, kBlock, kPaper>(cr, hr, mr, q, img, a.L, sorted, qpoint, nend, s_out, s_src,
+                                                    a.nbr, a.max_nbr);
                 const int32_t next = (anyl && cl >= 0) ? cl : ((anyr && cr >= 0) ? cr : rope);
                 // references always point forward; max() makes progress unconditional
                 v = uniform(max(next, v + 1));
