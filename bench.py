@@ -33,7 +33,7 @@ import hashlib  # noqa: E402
 
 METRIC = "nlist builds/s & pairs/s at 1 GPU vs oracle; batched vs plain; HBM GB/s %"
 HBM_PEAK_GBS = 8000.0
-BENCH_OPTS = {"leaf_size": 8, "qbits": 16, "block_size": 256}
+BENCH_OPTS = {"leaf_size": 16, "qbits": 16, "block_size": 128}
 WORKLOADS = {
     "lj8m": dict(n=8_000_000, rho=0.85, rc=3.0, skin=0.4, max_nbr=256),
     "lj1m": dict(n=1_000_000, rho=0.85, rc=3.0, skin=0.4, max_nbr=256),
@@ -103,7 +103,7 @@ def paper_mode(cfg, pos, steps: int) -> dict:
     cnt = torch.empty(n, dtype=torch.int32, device="cuda")
     ovf = torch.empty(1, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
-    out = {"workload": "same configuration, 10-bit grid, leaf 8, max_nbr 320"}
+    out = {"workload": f"same configuration, 10-bit grid, leaf {opts['leaf_size']}, max_nbr 320"}
     for name, mode in (("exact", Q.LIST_EXACT), ("paper", Q.LIST_PAPER)):
         for _ in range(2):
             Q.nlist_build_ex(tree, cfg.rcut, cfg.skin, 320, mode, nbr, cnt, ovf)

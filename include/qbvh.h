@@ -59,7 +59,7 @@ typedef void *qbvh_stream_t;  /* hipStream_t */
 
 enum {
     QBVH_OK = 0,
-    QBVH_EINVAL = -1, /* bad argument: NULL pointer, n outside 0..2^28-1, ntypes outside 1..4,
+    QBVH_EINVAL = -1, /* bad argument: NULL pointer, n outside 0..2^27-1, ntypes outside 1..4,
                          box edge <= 0 or not finite, skin < 0, rcut not symmetric,
                          max_nbr < 0, unsupported option value, or (with
                          validate) a coordinate outside [0, L) or a type outside
@@ -78,12 +78,12 @@ enum {
 typedef struct {
     int32_t leaf_size;  /* particles per leaf run: a subtree with at most this many
                            particles is not split further and its particles are
-                           tested one by one (1..8, default 8; 1 gives one particle
+                           tested one by one (1..16, default 16; 1 gives one particle
                            per leaf as in the paper) */
     int32_t qbits;      /* grid bits per axis for the quantized bounds (8..16,
                            default 16; the paper's layout uses 10) */
     int32_t block_size; /* traversal workgroup size: 64, 128, 192 or 256
-                           (default 256) */
+                           (default 128) */
     int32_t validate;   /* 1: check every coordinate and type on the device and
                            wait for the result (the call then synchronizes the
                            stream); 0 (default): inputs are trusted */
@@ -100,7 +100,7 @@ typedef struct {
  *   d_pos   device float [n][3], x y z of particle i at 3i..3i+2, every
  *           coordinate in [0, box[d]).
  *   d_type  device int32 [n] with values in [0, ntypes), or NULL when ntypes == 1.
- *   n       number of particles, 0 .. 2^28 - 1 (0: an empty tree, no work).
+ *   n       number of particles, 0 .. 2^27 - 1 (0: an empty tree, no work).
  *   ntypes  1..4; one tree is built per type (types with no particles give
  *           empty trees).
  *   box     host float [3]: orthorhombic periodic box edges, all > 0.
@@ -194,7 +194,7 @@ typedef struct {
  *   sys     host array [nsys]; each entry as for qbvh_build + nlist_build
  *           (d_pos/d_type/n/ntypes/box as qbvh_build, rcut/skin/max_nbr and
  *           the outputs as nlist_build).  Inputs are trusted (no device
- *           validation); the sum of n must stay below 2^28.
+ *           validation); the sum of n must stay below 2^27.
  *   opts    NULL or options; a zero field is chosen by the autotuner.
  *
  * Each system's outputs equal those of qbvh_build + nlist_build on that
@@ -263,7 +263,7 @@ typedef struct {
     int32_t max_inflight;     /* batches on the device at once, 1..8 (0: 2) */
     int32_t max_batch;        /* requests per batch, >= 1 (0: 64) */
     qbvh_batch_opts_t batch;  /* options of the batched launches; zero fields take
-                                 leaf 8, 16 bits, 256 work-items; graphs are not used
+                                 leaf 16, 16 bits, 128 work-items; graphs are not used
                                  (every batch has a new composition) */
 } qbvh_server_opts_t;
 
@@ -365,7 +365,7 @@ enum {
                                  words 0-2 left child box, 3-5 right child box
                                  (q_lo | q_hi << 16 per axis), 6 left child,
                                  7 right child: record index, or a particle run
-                                 ~((first << 3) | (count - 1)) */
+                                 ~((first << 4) | (count - 1)) */
     QBVH_EXPORT_ROPES = 13    /* int32 [nrecords] record that follows each record's subtree */
 };
 /* Internal node ids are sorted positions: the tree of the type occupying

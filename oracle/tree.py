@@ -38,7 +38,7 @@ Readings where the paper is silent (listed again in the design notes):
   split further), and a separate array holds its rope (the record after its
   subtree).  The left child's record is the next record.  Testing both child
   boxes in the parent halves the chain of dependent node loads of a walk.
-- A particle-run reference is ~((first << 3) | (count - 1)), negative; a
+- A particle-run reference is ~((first << 4) | (count - 1)), negative; a
   record reference is the record index, non-negative.  A tree of at most
   ``leaf_size`` particles has no record: its root is a run.
 """
@@ -152,7 +152,7 @@ def quantize_box(lo, hi, root_lo, h: float, qbits: int):
 
 def run_ref(first: int, count: int) -> int:
     """Reference to the particle run [first, first + count) (negative int32)."""
-    return ~((first << 3) | (count - 1))
+    return ~((first << 4) | (count - 1))
 
 
 def record_layout(sorted_pos, sorted_keys, ntypes: int, box, leaf_size: int = 1, qbits: int = 16):
@@ -167,7 +167,7 @@ def record_layout(sorted_pos, sorted_keys, ntypes: int, box, leaf_size: int = 1,
     each other in type order; ``meta[t]`` holds the tree's root reference,
     one past its last record, its root box and its grid spacing.
     """
-    assert 1 <= leaf_size <= 8
+    assert 1 <= leaf_size <= 16
     p = np.asarray(sorted_pos, dtype=np.float32).reshape(-1, 3)
     records, ropes, meta = [], [], []
     for t, (s, e) in enumerate(segments(sorted_keys, ntypes)):

@@ -29,9 +29,9 @@ thread_local int g_last_hip_error = 0;
 int resolve_opts(const qbvh_opts_t *in, qbvh_opts_t *out) {
     qbvh_opts_t o{};
     if (in) o = *in;
-    if (o.leaf_size == 0) o.leaf_size = 8;
+    if (o.leaf_size == 0) o.leaf_size = 16;
     if (o.qbits == 0) o.qbits = 16;
-    if (o.block_size == 0) o.block_size = 256;
+    if (o.block_size == 0) o.block_size = 128;
     if (!qbi::leaf_ok(o.leaf_size) || !qbi::qbits_ok(o.qbits) || !qbi::block_ok(o.block_size)) return QBVH_EINVAL;
     if (o.validate != 0 && o.validate != 1) return QBVH_EINVAL;
     *out = o;

@@ -170,11 +170,11 @@ hipError_t poll(BatchCtx &c, Plan &p, bool wait) {
 }
 
 // Candidate configurations: every fixed option as given, the free ones over
-// the values that matter on this hardware (leaf runs of 2, 4 and 8
+// the values that matter on this hardware (leaf runs of 4, 8 and 16
 // particles; workgroups of 64, 128 and 256; the paper's 10-bit grid and the
 // full 16-bit one).
 std::vector<Cfg> candidates(const qbvh_batch_opts_t &o) {
-    std::vector<int32_t> leaves = o.leaf_size ? std::vector<int32_t>{o.leaf_size} : std::vector<int32_t>{2, 4, 8};
+    std::vector<int32_t> leaves = o.leaf_size ? std::vector<int32_t>{o.leaf_size} : std::vector<int32_t>{4, 8, 16};
     std::vector<int32_t> bits = o.qbits ? std::vector<int32_t>{o.qbits} : std::vector<int32_t>{10, 16};
     std::vector<int32_t> blocks = o.block_size ? std::vector<int32_t>{o.block_size}
                                                : std::vector<int32_t>{64, 128, 256};

@@ -6,7 +6,7 @@
 //   words 0-2: quantized box of the left child,  w_d = q_lo_d | (q_hi_d << 16)
 //   words 3-5: quantized box of the right child, same packing
 //   word 6/7:  left/right child: record index (>= 0) or the particle run
-//              ~((first << 3) | (count - 1)) when the child holds at most
+//              ~((first << 4) | (count - 1)) when the child holds at most
 //              `leaf_size` particles
 // plus ropes[v], the record after v's subtree.  The left child's record is
 // the next record.  Storing both child boxes in the parent lets one step of

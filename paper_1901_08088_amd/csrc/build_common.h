@@ -37,8 +37,10 @@ struct Segment {
     int32_t s, e;
 };
 
-// Particle run [first, first + count), count <= 8, as a negative reference.
-__device__ __forceinline__ int32_t run_ref(int32_t first, int32_t count) { return ~((first << 3) | (count - 1)); }
+// Particle run [first, first + count), count <= 16, as a negative reference.
+__device__ __forceinline__ int32_t run_ref(int32_t first, int32_t count) {
+    return ~((first << kRunCountBits) | (count - 1));
+}
 
 // Common-prefix length of the augmented keys (key << 32 | position); -1
 // outside the segment.  Equal keys are told apart by position (Karras's rule).

@@ -18,6 +18,11 @@ __device__ __forceinline__ int32_t find_seg(const int32_t *__restrict__ first, i
     return lo;
 }
 
+// A particle run [first, first + count), count <= 16, is referenced as
+// ~((first << kRunCountBits) | (count - 1)).
+constexpr int kRunCountBits = 4;
+constexpr int32_t kRunCountMask = (1 << kRunCountBits) - 1;
+
 // Per-type tree description, written on the device after the bottom-up fit.
 struct TreeMeta {
     float lo[3];      // root-node box (exact fp32 min over the type's particles)
@@ -32,10 +37,11 @@ struct TreeMeta {
 };
 static_assert(sizeof(TreeMeta) == 64, "TreeMeta is 64 bytes");
 
-// The traversal loads a leaf run of up to 8 particles as 8 consecutive
-// float4 whatever its length; the sorted array carries this many spare
-// entries after its last particle so those loads stay inside the buffer.
-constexpr int32_t kSortedPad = 8;
+// The traversal loads the particles of a leaf run 8 float4 at a time from the
+// run's start and from its ninth particle, whatever the run's length; the
+// sorted array carries this many spare entries after its last particle so
+// those loads stay inside the buffer.
+constexpr int32_t kSortedPad = 16;
 
 // Device workspace of one built tree (all arrays sized for `cap` particles).
 struct Workspace {
@@ -119,8 +125,8 @@ struct BatchLaunch {
 };
 
 // Host helpers shared by the interface files.
-constexpr int32_t kMaxParticles = (1 << 28) - 1;  // particle runs store a sorted position in 28 bits
-inline bool leaf_ok(int32_t v) { return v >= 1 && v <= 8; }
+constexpr int32_t kMaxParticles = (1 << 27) - 1;  // particle runs store a sorted position in 27 bits
+inline bool leaf_ok(int32_t v) { return v >= 1 && v <= 16; }
 inline bool qbits_ok(int32_t v) { return v >= 8 && v <= 16; }
 // the traversal kernel is compiled for 64, 128, 192 and 256 work-items per group
 inline bool block_ok(int32_t v) { return v >= 64 && v <= 256 && (v % 64) == 0; }

@@ -84,9 +84,9 @@ __device__ __forceinline__ int32_t uniform(int32_t x) { return __builtin_amdgcn_
 // to its row kFlush at a time: with 16-byte aligned rows as two 16-byte
 // stores.  A candidate's index is written to the lane's next free slot
 // whether or not it is accepted, and the count advances only on acceptance,
-// so the per-candidate path has no branch.  A run holds at most 8 particles
-// and the ring is flushed after every run once kFlush entries wait, so no
-// more than 15 entries are ever pending.
+// so the per-candidate path has no branch.  Runs are taken 8 particles at a
+// time and the ring is flushed after each such part once kFlush entries wait,
+// so no more than 15 entries are ever pending.
 constexpr int kRing = 16;
 constexpr int kFlush = 8;
 
@@ -252,65 +252,71 @@ __device__ __forceinline__ void run_paper(const uint4 *__restrict__ qrun, uint32
     }
 }
 
-// Decide the particles of one hit run for the lanes with `hit` set.
+// Decide the particles of one hit run for the lanes with `hit` set.  A run
+// of up to 16 particles is taken in halves of at most 8: each half adds at
+// most 8 entries to a ring holding fewer than kFlush, and the ring is
+// flushed after every half.
 template <bool kVec4, int kBlock, bool kPaper>
 __device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, Lane &q, int img, const double (&L)[3],
                                          const float4 *__restrict__ sorted, const uint4 *__restrict__ qpoint,
                                          uint32_t nend, int32_t (*s_out)[kBlock], int32_t *s_src, int32_t *nbr,
                                          int32_t max_nbr) {
     const int32_t v = ~ref;
-    const uint32_t first = (uint32_t)uniform(v >> 3);
-    const uint32_t count = (uint32_t)uniform((v & 7) + 1);
+    const uint32_t first = (uint32_t)uniform(v >> kRunCountBits);
+    const uint32_t count = (uint32_t)uniform((v & kRunCountMask) + 1);
     // a well-formed tree never fails this; it keeps a corrupt reference from
     // reading outside the particle array
     if (first + count > nend) return;
-    const float4 *run = sorted + first;
     const float thr = hit ? q.r2in : -1.0f;
-    // the lane's own particle can only be accepted through the unshifted image
-    const uint32_t rel = (uint32_t)(q.k - (int32_t)first);
     const float out = hit ? q.r2out : -1.0f;
-    const bool self = img == 13 && __any(hit && rel < count);
-    if (kPaper) {
-        if (self)
-            run_paper<true, kBlock>(qpoint + first, count, rel, hit, q, s_out);
-        else
-            run_paper<false, kBlock>(qpoint + first, count, rel, hit, q, s_out);
-        if (__any(q.cnt - q.flushed >= kFlush) && q.cnt - q.flushed >= kFlush)
-            flush_ring<kVec4, kBlock>(q, s_out, nbr, max_nbr);
-        return;
-    }
-    bool shell;
     // (two 32-bit counts keep the comparison on the scalar unit)
-    if (!self && __popc((uint32_t)hits) + __popc((uint32_t)(hits >> 32)) <= 8) {
-        shell = run_sparse<kBlock>(run, count, hit, hits, thr, out, q, s_out, s_src);
-    } else {
-        const int32_t cnt0 = q.cnt;
-        const int32_t nout = self ? run_fp32<true, kBlock>(run, count, rel, thr, out, q, s_out)
-                                  : run_fp32<false, kBlock>(run, count, rel, thr, out, q, s_out);
-        shell = __any(nout != q.cnt - cnt0);
-    }
-    if (shell) {
-        // some pair lies in the shell around the cutoff: decide the shell
-        // pairs with the definition's fp64 arithmetic
-        const double sx = (double)(img % 3 - 1) * L[0];
-        const double sy = (double)((img / 3) % 3 - 1) * L[1];
-        const double sz = (double)(img / 9 - 1) * L[2];
-        for (uint32_t j = 0; j < count; ++j) {
-            const float4 p = run[j];
-            const float ax = p.x - q.qsx, ay = p.y - q.qsy, az = p.z - q.qsz;
-            const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
-            if (hit && !(d2 <= thr) && d2 <= q.r2out && j != rel) {
-                const double dx = ((double)p.x - (double)q.x) - sx;
-                const double dy = ((double)p.y - (double)q.y) - sy;
-                const double dz = ((double)p.z - (double)q.z) - sz;
-                if ((dx * dx + dy * dy) + dz * dz <= q.r2) {
-                    s_out[q.cnt & (kRing - 1)][threadIdx.x] = ~__float_as_int(p.w);
-                    ++q.cnt;
+    const bool sparse = __popc((uint32_t)hits) + __popc((uint32_t)(hits >> 32)) <= 8;
+    for (uint32_t h0 = 0; h0 < count; h0 += 8) {
+        const uint32_t c8 = count - h0 < 8u ? count - h0 : 8u;
+        const float4 *run = sorted + first + h0;
+        // the lane's own particle can only be accepted through the unshifted image
+        const uint32_t rel = (uint32_t)(q.k - (int32_t)(first + h0));
+        const bool self = img == 13 && __any(hit && rel < c8);
+        if (kPaper) {
+            if (self)
+                run_paper<true, kBlock>(qpoint + first + h0, c8, rel, hit, q, s_out);
+            else
+                run_paper<false, kBlock>(qpoint + first + h0, c8, rel, hit, q, s_out);
+        } else {
+            bool shell;
+            if (!self && sparse) {
+                shell = run_sparse<kBlock>(run, c8, hit, hits, thr, out, q, s_out, s_src);
+            } else {
+                const int32_t cnt0 = q.cnt;
+                const int32_t nout = self ? run_fp32<true, kBlock>(run, c8, rel, thr, out, q, s_out)
+                                          : run_fp32<false, kBlock>(run, c8, rel, thr, out, q, s_out);
+                shell = __any(nout != q.cnt - cnt0);
+            }
+            if (shell) {
+                // some pair lies in the shell around the cutoff: decide the
+                // shell pairs with the definition's fp64 arithmetic
+                const double sx = (double)(img % 3 - 1) * L[0];
+                const double sy = (double)((img / 3) % 3 - 1) * L[1];
+                const double sz = (double)(img / 9 - 1) * L[2];
+                for (uint32_t j = 0; j < c8; ++j) {
+                    const float4 p = run[j];
+                    const float ax = p.x - q.qsx, ay = p.y - q.qsy, az = p.z - q.qsz;
+                    const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
+                    if (hit && !(d2 <= thr) && d2 <= q.r2out && j != rel) {
+                        const double dx = ((double)p.x - (double)q.x) - sx;
+                        const double dy = ((double)p.y - (double)q.y) - sy;
+                        const double dz = ((double)p.z - (double)q.z) - sz;
+                        if ((dx * dx + dy * dy) + dz * dz <= q.r2) {
+                            s_out[q.cnt & (kRing - 1)][threadIdx.x] = ~__float_as_int(p.w);
+                            ++q.cnt;
+                        }
+                    }
                 }
             }
         }
+        if (__any(q.cnt - q.flushed >= kFlush) && q.cnt - q.flushed >= kFlush)
+            flush_ring<kVec4, kBlock>(q, s_out, nbr, max_nbr);
     }
-    if (__any(q.cnt - q.flushed >= kFlush) && q.cnt - q.flushed >= kFlush) flush_ring<kVec4, kBlock>(q, s_out, nbr, max_nbr);
 }
 
 // The read-only arrays come as separate __restrict__ parameters: that lets the

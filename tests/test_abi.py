@@ -44,7 +44,7 @@ def test_workspace_bytes():
     assert 100 < b / 1_000_000 < 200  # about 128 bytes per particle
     assert Q.qbvh_workspace_bytes(-1) == 0
     assert Q.qbvh_workspace_bytes(10, ntypes=5) == 0
-    assert Q.qbvh_workspace_bytes(10, opts={"leaf_size": 9}) == 0
+    assert Q.qbvh_workspace_bytes(10, opts={"leaf_size": 17}) == 0
 
 
 def _build_rc(n=10, ntypes=1, box=(5.0, 5.0, 5.0), opts=None, pos=1, typ=None, tree_ptr=True):
@@ -68,7 +68,7 @@ def _build_rc(n=10, ntypes=1, box=(5.0, 5.0, 5.0), opts=None, pos=1, typ=None, t
     dict(box=(float("inf"), 5.0, 5.0)),
     dict(pos=0),
     dict(ntypes=2, typ=None),
-    dict(opts={"leaf_size": 9}),
+    dict(opts={"leaf_size": 17}),
     dict(opts={"leaf_size": -1}),
     dict(opts={"qbits": 7}),
     dict(opts={"qbits": 17}),
@@ -127,7 +127,7 @@ def _batch_rc(opts=None, **over):
 
 @pytest.mark.parametrize("over,code", [
     (dict(n=-1), capi.EINVAL),
-    (dict(n=1 << 28), capi.EINVAL),
+    (dict(n=1 << 27), capi.EINVAL),
     (dict(ntypes=0), capi.EINVAL),
     (dict(ntypes=2, rcut=[3.0, 2.0, 2.5, 3.0]), capi.EINVAL),  # types missing and rcut not symmetric
     (dict(box=(10.0, -1.0, 10.0)), capi.EINVAL),
@@ -143,7 +143,7 @@ def test_batch_rejects_bad_systems_without_device_work(over, code):
     assert _batch_rc(**over) == code
 
 
-@pytest.mark.parametrize("opts", [dict(leaf_size=9), dict(qbits=17), dict(block_size=96), dict(eager=2)])
+@pytest.mark.parametrize("opts", [dict(leaf_size=17), dict(qbits=17), dict(block_size=96), dict(eager=2)])
 def test_batch_rejects_bad_options_without_device_work(opts):
     assert _batch_rc(opts) == capi.EINVAL
 

@@ -49,7 +49,8 @@ def _plain_counts(cfgs, max_nbr):
 
 @pytest.mark.parametrize("opts", [dict(leaf_size=4, qbits=16, block_size=128, eager=1),
                                   dict(leaf_size=1, qbits=10, block_size=64, eager=0),
-                                  dict(leaf_size=8, qbits=12, block_size=256, eager=0)])
+                                  dict(leaf_size=8, qbits=12, block_size=256, eager=0),
+                                  dict(leaf_size=16, qbits=16, block_size=64, eager=0)])
 def test_batch_matches_oracle_and_plain(opts):
     require_gpu()
     cfgs = _mixed_systems()
@@ -106,7 +107,7 @@ def test_batch_autotuner_freezes_and_stays_exact():
             break
         assert calls <= 2 * st["candidates"] + 8, st
     print(f"[batch] tuned after {calls} calls: {st}", flush=True)
-    assert st["leaf_size"] in (2, 4, 8) and st["qbits"] in (10, 16) and st["block_size"] in (64, 128, 256)
+    assert st["leaf_size"] in (4, 8, 16) and st["qbits"] in (10, 16) and st["block_size"] in (64, 128, 256)
     for s in systems:
         s["count"].fill_(-1)
         s["nbr"].fill_(-7)

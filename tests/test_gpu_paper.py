@@ -45,7 +45,7 @@ def _check(cfg, qbits, nbr, cnt, ovf, max_nbr):
     return float(cnt.sum() - (ex_rp[-1])) / cfg.n
 
 
-@pytest.mark.parametrize("leaf,qbits", [(1, 10), (4, 10), (8, 10), (8, 16), (3, 8)])
+@pytest.mark.parametrize("leaf,qbits", [(1, 10), (4, 10), (8, 10), (8, 16), (3, 8), (16, 10), (12, 10)])
 def test_paper_mode_lj4000(leaf, qbits):
     cfg = W.lj_fluid(4000)
     nbr, cnt, ovf = _paper_rows(cfg, {"leaf_size": leaf, "qbits": qbits})

@@ -77,7 +77,7 @@ def test_build_steps_sizes(n):
     _step_parity(W.Config(pos=pos, box=box, rcut=np.array([[2.0]], np.float32), skin=0.3))
 
 
-@pytest.mark.parametrize("leaf_size,qbits", [(1, 10), (4, 16), (8, 12)])
+@pytest.mark.parametrize("leaf_size,qbits", [(1, 10), (4, 16), (8, 12), (16, 16), (11, 10)])
 def test_build_steps_lj4000(leaf_size, qbits):
     _step_parity(W.lj_fluid(4000), leaf_size=leaf_size, qbits=qbits)
 
@@ -110,6 +110,7 @@ def test_lj4000_exact_lists_and_determinism():
 
 
 @pytest.mark.parametrize("opts", [{"leaf_size": 1, "qbits": 10}, {"leaf_size": 4}, {"leaf_size": 8, "qbits": 12},
+                                  {"leaf_size": 16}, {"leaf_size": 13, "qbits": 10, "block_size": 128},
                                   {"block_size": 64}, {"block_size": 192, "leaf_size": 2}])
 def test_lj4000_options(opts):
     cfg = W.lj_fluid(4000)

@@ -169,7 +169,7 @@ def _run(ref):
     """Decode a particle-run reference: (first, count)."""
     ref = int(ref)
     v = ~(ref - (1 << 32) if ref >= (1 << 31) else ref)
-    return v >> 3, (v & 7) + 1
+    return v >> 4, (v & 15) + 1
 
 
 def _alg1_rows(records, ropes, meta, box, rlist2, qtypes, qpos, orig_of_query, sorted_pos, perm,
@@ -239,7 +239,7 @@ def _alg1_rows(records, ropes, meta, box, rlist2, qtypes, qpos, orig_of_query, s
     return rows
 
 
-@pytest.mark.parametrize("leaf_size,qbits", [(1, 16), (1, 10), (3, 16), (8, 12)])
+@pytest.mark.parametrize("leaf_size,qbits", [(1, 16), (1, 10), (3, 16), (8, 12), (16, 16), (13, 10)])
 def test_layout_traversal_reproduces_brute_force(leaf_size, qbits):
     cfg = W.lj_fluid(350, seed=8, rho=0.6, rc=2.0, skin=0.3)
     b = T.build_all(cfg.pos, cfg.box, leaf_size=leaf_size, qbits=qbits)
@@ -281,7 +281,7 @@ def test_layout_tree_smaller_than_a_leaf_run():
 
 def test_layout_ropes_and_children():
     cfg = W.lj_fluid(500, seed=9)
-    for leaf_size in (1, 2, 5):
+    for leaf_size in (1, 2, 5, 16):
         b = T.build_all(cfg.pos, cfg.box, leaf_size=leaf_size)
         rec, ropes = b["records"], b["ropes"]
         (m,) = b["meta"]
