@@ -124,17 +124,18 @@ __global__ __launch_bounds__(kBuildThreads) void k_karras(const uint32_t *__rest
 // sorted position into chunks.  A node whose particle range lies inside one
 // chunk has both children inside it, so only that chunk's workgroup ever
 // touches its counter.  Level 0 uses chunks of kFitChunk positions with
-// counters and boxes in LDS; every further level multiplies the chunk by
+// counters and boxes in LDS (60 KB, so two workgroups share a compute unit);
+// every further level multiplies the chunk by
 // kFitFanout and climbs in global memory with workgroup-scope atomics,
 // starting from the nodes the previous level left at its chunk borders (the
 // "frontier": finished nodes whose parent straddles a border).  The last
 // level has one chunk and reaches every root.  A frontier holds at most two
 // border chains of the tree (each at most 65 deep), so kFrontierCap suffices.
-constexpr int kFitChunk = 2048;
+constexpr int kFitChunk = 1024;
 constexpr int kFitThreads = 1024;
-// A small fanout keeps every level's climbs short (about four tree levels from
+// A small fanout keeps every level's climbs short (about five tree levels from
 // each frontier node) and its workgroups many; N = 8M takes three level launches.
-constexpr int kFitFanout = 16;
+constexpr int kFitFanout = 32;
 constexpr int kFrontierCap = 160;
 
 __device__ __forceinline__ void frontier_push(int32_t c, uint32_t *s_fcount, int32_t *s_front, int32_t *err) {
