@@ -58,7 +58,13 @@ def traversal_bytes(n: int, nrecords: int, stored_pairs: int) -> int:
 # factor the same counters read for a plain elementwise copy of known size (the
 # --copy-probe-mib kernel).  Valid only for the kernel sources it was taken on:
 # ``traffic`` is reported as null once their hash differs.
-TRAFFIC = None
+TRAFFIC = {"sources": "989fe0bebfe1918f", "workload": "lj8m",
+           "opts": {"leaf_size": 16, "qbits": 16, "block_size": 128},
+           "fetch_kib": 1448174.79, "write_kib": 6571451.40, "copy_factor": 1.0,
+           "fetch_factor": 0.500022, "profile": "profiles/k_traverse_lj8m_counters.md",
+           # SQ_ACTIVE_INST_VALU / (SIMDs x kernel cycles / 4): the VALU issues one wave64
+           # instruction per 4 cycles per SIMD, so this is the kernel's VALU issue roofline
+           "valu_busy": 0.94}
 KERNEL_SOURCES = ("paper_1901_08088_amd/csrc/traverse.hip", "paper_1901_08088_amd/csrc/qbvh_internal.h")
 
 
@@ -74,7 +80,9 @@ def measured_traffic(workload: str, opts: dict):
     t = TRAFFIC
     if t is None or t["sources"] != kernel_source_hash() or t["workload"] != workload or t["opts"] != opts:
         return None
-    return (t["fetch_kib"] + t["write_kib"]) * 1024.0 / t["copy_factor"]
+    # each counter scaled by what it reads for the copy probe (FETCH_SIZE counts
+    # half of the bytes read on this part, WRITE_SIZE all bytes written)
+    return (t["fetch_kib"] / t["fetch_factor"] + t["write_kib"] / t["copy_factor"]) * 1024.0
 
 
 def copy_probe(mib: int) -> None:
@@ -431,6 +439,8 @@ def main(argv=None) -> int:
         "roofline": {"kernel": "k_traverse", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, opts),
+                     "valu_busy": (TRAFFIC["valu_busy"] if measured_traffic(args.workload, opts) is not None
+                                   else None),
                      "algorithmic_bytes": tbytes, "kernel_sources": kernel_source_hash()},
         "cpu_baseline": base,
         "paper_mode": paper,
