@@ -176,6 +176,11 @@ void launch(qbvh_server &s, size_t li) {
             ++it;
             continue;
         }
+        // a batch holds at most kMaxParticles in all (the request waits for a later batch)
+        if (total + r.n > qbi::kMaxParticles) {
+            ++it;
+            continue;
+        }
         const bool fits_buffers = sit != s.sessions.end() && sit->second.cap_n >= r.n &&
                                   sit->second.cap_nbr >= r.max_nbr && sit->second.mem;
         const size_t new_bytes = fits_buffers ? 0 : session_bytes(r.n, r.max_nbr);

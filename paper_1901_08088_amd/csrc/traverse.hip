@@ -133,6 +133,11 @@ __device__ __forceinline__ int32_t orig_of(float w) {
     return r;
 }
 
+// Particle u of a run, addressed as the array base plus a byte offset.
+__device__ __forceinline__ float4 particle(const char *__restrict__ base, uint32_t off, uint32_t u) {
+    return reinterpret_cast<const float4 *>(base + off)[u];
+}
+
 // fp32 pass over the particles of a run for every lane.  Accepts what is
 // surely in (d2 <= thr; thr = r2in for hitting lanes, -1 otherwise) and
 // counts in `nout` the pairs with d2 <= out (out = r2out for hitting lanes,
@@ -142,11 +147,11 @@ __device__ __forceinline__ int32_t orig_of(float w) {
 // up front.  kSelf: the run may hold the lane's own particle at index `rel`,
 // which is never listed (nor counted in nout).
 template <bool kSelf, int kBlock>
-__device__ __forceinline__ int32_t run_fp32(const float4 *__restrict__ run, uint32_t count, uint32_t rel,
+__device__ __forceinline__ int32_t run_fp32(const char *__restrict__ base, uint32_t roff, uint32_t count, uint32_t rel,
                                             float thr, float out, Lane &q, int32_t (*s_out)[kBlock]) {
     float4 p[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) p[u] = run[u];
+    for (int u = 0; u < 8; ++u) p[u] = particle(base, roff, (uint32_t)u);
     // both halves of the run are requested before the first test (the
     // compiler would otherwise delay the second load behind the early exits)
     asm volatile("" ::"s"(p[0].x), "s"(p[4].x));
@@ -178,14 +183,15 @@ __device__ __forceinline__ int32_t run_fp32(const float4 *__restrict__ run, uint
 // 64-entry LDS table rank -> lane.  Every cross-lane read runs on all lanes:
 // a lane left out of one would hand its readers 0.
 template <int kBlock>
-__device__ __forceinline__ bool run_sparse(const float4 *__restrict__ run, uint32_t count, bool hit, uint64_t hits,
+__device__ __forceinline__ bool run_sparse(const char *__restrict__ base, uint32_t roff, uint32_t count, bool hit,
+                                           uint64_t hits,
                                            float thr, float out, Lane &q, int32_t (*s_out)[kBlock],
                                            int32_t *s_src) {
     const uint32_t lane = __lane_id();
     const uint32_t i = lane >> 3, j = lane & 7u;
     const uint32_t h = (uint32_t)__popcll(hits);
     const bool pv = i < h && j < count;
-    const float4 p = run[j];  // j < 8: inside the run or its padding
+    const float4 p = particle(base, roff, j);  // j < 8: inside the run or its padding
     const uint32_t rank =
         __builtin_amdgcn_mbcnt_hi((uint32_t)(hits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hits, 0u));
     if (hit) s_src[rank] = (int32_t)lane;
@@ -273,7 +279,8 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, L
     const bool sparse = __popc((uint32_t)hits) + __popc((uint32_t)(hits >> 32)) <= 8;
     for (uint32_t h0 = 0; h0 < count; h0 += 8) {
         const uint32_t c8 = count - h0 < 8u ? count - h0 : 8u;
-        const float4 *run = sorted + first + h0;
+        const char *sbase = reinterpret_cast<const char *>(sorted);
+        const uint32_t roff = (first + h0) * 16u;
         // the lane's own particle can only be accepted through the unshifted image
         const uint32_t rel = (uint32_t)(q.k - (int32_t)(first + h0));
         const bool self = img == 13 && __any(hit && rel < c8);
@@ -285,11 +292,11 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, L
         } else {
             bool shell;
             if (!self && sparse) {
-                shell = run_sparse<kBlock>(run, c8, hit, hits, thr, out, q, s_out, s_src);
+                shell = run_sparse<kBlock>(sbase, roff, c8, hit, hits, thr, out, q, s_out, s_src);
             } else {
                 const int32_t cnt0 = q.cnt;
-                const int32_t nout = self ? run_fp32<true, kBlock>(run, c8, rel, thr, out, q, s_out)
-                                          : run_fp32<false, kBlock>(run, c8, rel, thr, out, q, s_out);
+                const int32_t nout = self ? run_fp32<true, kBlock>(sbase, roff, c8, rel, thr, out, q, s_out)
+                                          : run_fp32<false, kBlock>(sbase, roff, c8, rel, thr, out, q, s_out);
                 shell = __any(nout != q.cnt - cnt0);
             }
             if (shell) {
@@ -299,7 +306,7 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, L
                 const double sy = (double)((img / 3) % 3 - 1) * L[1];
                 const double sz = (double)(img / 9 - 1) * L[2];
                 for (uint32_t j = 0; j < c8; ++j) {
-                    const float4 p = run[j];
+                    const float4 p = particle(sbase, roff, j);
                     const float ax = p.x - q.qsx, ay = p.y - q.qsy, az = p.z - q.qsz;
                     const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
                     if (hit && !(d2 <= thr) && d2 <= q.r2out && j != rel) {
