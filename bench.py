@@ -38,7 +38,26 @@ WORKLOADS = {
     "lj8m": dict(n=8_000_000, rho=0.85, rc=3.0, skin=0.4, max_nbr=256),
     "lj1m": dict(n=1_000_000, rho=0.85, rc=3.0, skin=0.4, max_nbr=256),
     "lj4000": dict(n=4000, rho=0.85, rc=3.0, skin=0.4, max_nbr=256),
+    # two-type colloid/solvent mixture (one tree per type), 2% colloids of diameter 5
+    "colloid1m": dict(n=1_000_000, kind="colloid", skin=0.4, max_nbr=256),
 }
+
+
+def make_config(wl: dict):
+    if wl.get("kind") == "colloid":
+        return W.colloid_solvent(wl["n"], skin=wl["skin"])
+    return W.lj_fluid(wl["n"], rho=wl["rho"], rc=wl["rc"], skin=wl["skin"])
+
+
+def describe(wl: dict, cfg) -> str:
+    if wl.get("kind") == "colloid":
+        m = cfg.meta
+        return (f"colloid_solvent N={cfg.n:,} ({m['n_colloid']:,} colloids d=5, {m['n_solvent']:,} solvent, "
+                f"L={m['L']:.2f}, colloid volume fraction {m['colloid_volume_fraction']:.3f}) rc_ij=(d_i+d_j)/2 "
+                f"skin={wl['skin']} max_nbr={wl['max_nbr']} fp32, one tree per type (RSA placement, seed "
+                f"{m['seed']})")
+    return (f"lj_fluid N={cfg.n:,} rho={wl['rho']} rc={wl['rc']} skin={wl['skin']} "
+            f"max_nbr={wl['max_nbr']} fp32 (jittered simple-cubic lattice, seed {cfg.meta['seed']})")
 
 
 def log(msg: str) -> None:
@@ -130,6 +149,40 @@ def paper_mode(cfg, pos, steps: int) -> dict:
     del nbr
     torch.cuda.empty_cache()
     log(f"paper mode: {out}")
+    return out
+
+
+def single_graph(cfg, pos, types, max_nbr: int, steps: int) -> dict:
+    """The same system as a one-system nlist_build_many call with the bench's
+    options fixed (no autotuning): build + traversal replayed from one captured
+    hipGraph, against the same work launched kernel by kernel."""
+    import torch
+    import paper_1901_08088_amd as Q
+    n = cfg.n
+    y = dict(pos=pos, types=types, ntypes=cfg.ntypes, box=cfg.box, rcut=cfg.rcut, skin=cfg.skin,
+             max_nbr=max_nbr, nbr=torch.empty((n, max_nbr), dtype=torch.int32, device="cuda"),
+             count=torch.empty(n, dtype=torch.int32, device="cuda"),
+             overflow=torch.empty(1, dtype=torch.int32, device="cuda"))
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, eager in (("graph", 0), ("eager", 1)):
+        o = dict(BENCH_OPTS, eager=eager)
+        for _ in range(3):
+            Q.nlist_build_many([y], o)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(steps):
+            Q.nlist_build_many([y], o)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        out[f"{name}_ms"] = ev[0].elapsed_time(ev[1]) / steps
+    out["pairs"] = int(y["count"].sum())
+    out["graph_builds_per_s"] = 1e3 / out["graph_ms"]
+    Q.nlist_batch_release()
+    del y
+    torch.cuda.empty_cache()
+    log(f"one-system batched call: {out}")
     return out
 
 
@@ -299,7 +352,8 @@ def cpu_baseline(cfg, sample_rows: int) -> dict:
     q = np.sort(rng.choice(n, min(sample_rows, n), replace=False)) if sample_rows < n else None
     nq = n if q is None else q.size
     t0 = time.perf_counter()
-    rp, _ = oracle.neighbor_lists(cfg.pos, cfg.box, cfg.rcut, cfg.skin, queries=q, method="cells")
+    rp, _ = oracle.neighbor_lists(cfg.pos, cfg.box, cfg.rcut, cfg.skin, types=cfg.types, queries=q,
+                                  method="cells")
     dt = time.perf_counter() - t0
     full = dt * n / nq
     return {"value": 1.0 / full, "unit": "nlist builds/s", "cores": oracle.max_threads(), "kind": "oracle",
@@ -321,6 +375,8 @@ def main(argv=None) -> int:
                     help="oracle rows timed for the CPU baseline (0 = skip)")
     ap.add_argument("--paper-steps", type=int, default=10,
                     help="traversals timed for the exact-vs-paper-mode comparison (0 = skip)")
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="one-system graph-replayed calls timed on the same workload (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=20,
                     help="passes timed for the batched-vs-plain ensemble comparison (0 = skip)")
     ap.add_argument("--served-seconds", type=float, default=5.0,
@@ -341,21 +397,22 @@ def main(argv=None) -> int:
 
     wl = WORKLOADS[args.workload]
     log(f"generating {args.workload}")
-    cfg = W.lj_fluid(wl["n"], rho=wl["rho"], rc=wl["rc"], skin=wl["skin"])
+    cfg = make_config(wl)
     n, max_nbr = cfg.n, wl["max_nbr"]
     opts = {"leaf_size": args.leaf_size, "qbits": args.qbits, "block_size": args.block_size}
 
     pos = torch.from_numpy(cfg.pos).cuda()
+    types = None if cfg.types is None else torch.from_numpy(cfg.types).cuda()
     nbr = torch.empty((n, max_nbr), dtype=torch.int32, device="cuda")
     cnt = torch.empty(n, dtype=torch.int32, device="cuda")
     ovf = torch.empty(1, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
-    tree = Q.qbvh_build(pos, None, cfg.box, 1, opts)
+    tree = Q.qbvh_build(pos, types, cfg.box, cfg.ntypes, opts)
 
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        Q.qbvh_build(pos, None, cfg.box, 1, opts, tree=tree)
+        Q.qbvh_build(pos, types, cfg.box, cfg.ntypes, opts, tree=tree)
         if ev is not None:
             ev[1].record(stream)
         Q.nlist_build(tree, cfg.rcut, cfg.skin, max_nbr, nbr, cnt, ovf)
@@ -393,9 +450,14 @@ def main(argv=None) -> int:
         copy_probe(args.copy_probe_mib)
 
     paper = None
-    if args.paper_steps > 0:
+    if args.paper_steps > 0 and cfg.types is None:
         log("paper-mode lists (10-bit grid)")
         paper = paper_mode(cfg, pos, args.paper_steps)
+
+    graph = None
+    if args.graph_steps > 0:
+        log("one-system graph replay")
+        graph = single_graph(cfg, pos, types, max_nbr, args.graph_steps)
 
     batched = None
     if args.batched_steps > 0:
@@ -428,9 +490,7 @@ def main(argv=None) -> int:
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"lj_fluid N={n:,} rho={wl['rho']} rc={wl['rc']} skin={wl['skin']} "
-                               f"max_nbr={max_nbr} fp32 (jittered simple-cubic lattice, seed "
-                               f"{cfg.meta['seed']})",
+        "config": {"workload": describe(wl, cfg),
                    "n": n, "max_nbr": max_nbr, "opts": opts, "parallelism": "single GPU"},
         "pairs_per_s": pairs * builds_per_s,
         "directed_pairs": pairs,
@@ -444,6 +504,7 @@ def main(argv=None) -> int:
                      "algorithmic_bytes": tbytes, "kernel_sources": kernel_source_hash()},
         "cpu_baseline": base,
         "paper_mode": paper,
+        "single_graph": graph,
         "batched": batched,
         "served": serve,
     }
