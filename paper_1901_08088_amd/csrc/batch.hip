@@ -48,14 +48,10 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_init(int32_t nsys, uint32_t
 __global__ __launch_bounds__(kBuildThreads) void k_b_morton(const int32_t *__restrict__ blk_first, int32_t nsys,
                                                             const SysBuild *__restrict__ sysb, int32_t total,
                                                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                            uint32_t *__restrict__ kept,
-                                                            uint32_t *__restrict__ type_count) {
-    __shared__ uint32_t s_cnt[QBVH_MAX_TYPES];
+                                                            uint32_t *__restrict__ kept) {
     const Item it = item_of(blk_first, nsys);
     const SysBuild &y = sysb[it.sys];
-    if (threadIdx.x < QBVH_MAX_TYPES) s_cnt[threadIdx.x] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) kept[total] = 0;
-    __syncthreads();
     if (it.local < y.n) {
         const int32_t k = y.off + it.local;
         kept[k] = 0;
@@ -66,11 +62,19 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_morton(const int32_t *__res
         t = t < 0 ? 0 : (t >= y.ntypes ? y.ntypes - 1 : t);
         keys[k] = morton_key(x, yy, z, y.scale[0], y.scale[1], y.scale[2], t);
         vals[k] = (uint32_t)k;
-        atomicAdd(&s_cnt[t], 1u);
     }
-    __syncthreads();
-    if (threadIdx.x < QBVH_MAX_TYPES && s_cnt[threadIdx.x])
-        atomicAdd(&type_count[it.sys * QBVH_MAX_TYPES + threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+// Particles per (system, type), read off each system's sorted keys by binary
+// search (every entry written, types a system lacks included).
+__global__ __launch_bounds__(kBuildThreads) void k_b_type_count(int32_t nsys, const SysBuild *__restrict__ sysb,
+                                                                const uint32_t *__restrict__ keys,
+                                                                uint32_t *__restrict__ type_count) {
+    const int32_t i = blockIdx.x * kBuildThreads + threadIdx.x;
+    if (i >= nsys * QBVH_MAX_TYPES) return;
+    const SysBuild &y = sysb[i / QBVH_MAX_TYPES];
+    const uint32_t t = (uint32_t)(i % QBVH_MAX_TYPES);
+    type_count[i] = (uint32_t)(type_start(keys, y.off, y.off + y.n, t + 1) - type_start(keys, y.off, y.off + y.n, t));
 }
 
 // Sorted particle k of system s as float4 (x, y, z, bits of ~local input index).
@@ -187,10 +191,12 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t s) {
                        0, s, b.nsys, b.type_count, b.trav, w.err);
     if (b.blocks > 0)
         hipLaunchKernelGGL(k_b_morton, dim3((unsigned)b.blocks), dim3(kBuildThreads), 0, s, b.blk_first, b.nsys,
-                           b.sysb, b.total, w.keys, w.vals, w.kept, b.type_count);
+                           b.sysb, b.total, w.keys, w.vals, w.kept);
     hipError_t e = launch_radix_sort_segmented(w.keys, w.vals, w.keys2, w.vals2, b.hist, b.scan_part, b.total,
                                                b.tiles, b.tile_first, b.sys_off, b.nsys, s);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_b_type_count, dim3((unsigned)((ninit + kBuildThreads - 1) / kBuildThreads)),
+                       dim3(kBuildThreads), 0, s, b.nsys, b.sysb, w.keys, b.type_count);
     if (b.total > 0) {
         hipLaunchKernelGGL(k_b_gather, dim3((unsigned)b.blocks), dim3(kBuildThreads), 0, s, b.blk_first, b.nsys,
                            b.sysb, w.vals, w.sorted);

@@ -43,13 +43,9 @@ __global__ __launch_bounds__(kBuildThreads) void k_morton(const float *__restric
                                                           int32_t ntypes, float Lx, float Ly, float Lz,
                                                           double sx, double sy, double sz, int32_t validate,
                                                           uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                          uint32_t *__restrict__ kept,
-                                                          uint32_t *__restrict__ type_count, int32_t *err) {
-    __shared__ uint32_t s_cnt[QBVH_MAX_TYPES];
+                                                          uint32_t *__restrict__ kept, int32_t *err) {
     const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
-    if (threadIdx.x < QBVH_MAX_TYPES) s_cnt[threadIdx.x] = 0;
     if (k <= n) kept[k] = 0;
-    __syncthreads();
     if (k < n) {
         const float x = pos[3 * (int64_t)k + 0];
         const float y = pos[3 * (int64_t)k + 1];
@@ -63,11 +59,15 @@ __global__ __launch_bounds__(kBuildThreads) void k_morton(const float *__restric
         t = t < 0 ? 0 : (t >= ntypes ? ntypes - 1 : t);
         keys[k] = morton_key(x, y, z, sx, sy, sz, t);
         vals[k] = (uint32_t)k;
-        if (ntypes > 1) atomicAdd(&s_cnt[t], 1u);
     }
-    __syncthreads();
-    if (ntypes > 1 && threadIdx.x < (unsigned)ntypes && s_cnt[threadIdx.x])
-        atomicAdd(&type_count[threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+// Particles per type, read off the sorted keys (type in bits 30-31) by binary
+// search: no atomics on a few hot counters.
+__global__ void k_type_count(const uint32_t *__restrict__ keys, int32_t n, uint32_t *__restrict__ type_count) {
+    const uint32_t t = threadIdx.x;
+    if (t < QBVH_MAX_TYPES)
+        type_count[t] = (uint32_t)(type_start(keys, 0, n, t + 1) - type_start(keys, 0, n, t));
 }
 
 __global__ __launch_bounds__(kBuildThreads) void k_gather(const float *__restrict__ pos,
@@ -478,9 +478,10 @@ hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d
     const double sy = 1023.0 / (double)box[1];
     const double sz = 1023.0 / (double)box[2];
     hipLaunchKernelGGL(k_morton, grid_for((int64_t)n + 1), dim3(kBuildThreads), 0, s, d_pos, d_type, n, ntypes,
-                       box[0], box[1], box[2], sx, sy, sz, validate, w.keys, w.vals, w.kept, w.type_count, w.err);
+                       box[0], box[1], box[2], sx, sy, sz, validate, w.keys, w.vals, w.kept, w.err);
     hipError_t e = launch_radix_sort(w.keys, w.vals, w.keys2, w.vals2, w.hist, w.digit_total, n, w.tiles, s);
     if (e != hipSuccess) return e;
+    if (ntypes > 1) hipLaunchKernelGGL(k_type_count, dim3(1), dim3(64), 0, s, w.keys, n, w.type_count);
     if (n > 0) {
         hipLaunchKernelGGL(k_gather, grid_for(n), dim3(kBuildThreads), 0, s, d_pos, w.vals, n, w.sorted);
         hipLaunchKernelGGL(k_karras, grid_for(n), dim3(kBuildThreads), 0, s, w.keys, n, ntypes, w.type_count,

@@ -37,6 +37,19 @@ struct Segment {
     int32_t s, e;
 };
 
+// First position in [lo, hi) of sorted keys whose type (bits 30-31) is at
+// least t; hi when there is none.
+__device__ __forceinline__ int32_t type_start(const uint32_t *__restrict__ keys, int32_t lo, int32_t hi, uint32_t t) {
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if ((keys[mid] >> 30) < t)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // Particle run [first, first + count), count <= 16, as a negative reference.
 __device__ __forceinline__ int32_t run_ref(int32_t first, int32_t count) {
     return ~((first << kRunCountBits) | (count - 1));
