@@ -262,8 +262,8 @@ __device__ __forceinline__ void run_paper(const uint4 *__restrict__ qrun, uint32
 // of up to 16 particles is taken in halves of at most 8: each half adds at
 // most 8 entries to a ring holding fewer than kFlush, and the ring is
 // flushed after every half.
-template <bool kVec4, int kBlock, bool kPaper>
-__device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, Lane &q, int img, const double (&L)[3],
+template <bool kVec4, int kBlock, bool kPaper, class LArr>
+__device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, Lane &q, int img, const LArr &L,
                                          const float4 *__restrict__ sorted, const uint4 *__restrict__ qpoint,
                                          uint32_t nend, int32_t (*s_out)[kBlock], int32_t *s_src, int32_t *nbr,
                                          int32_t max_nbr) {
@@ -328,8 +328,8 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, L
 
 // The read-only arrays come as separate __restrict__ parameters: that lets the
 // compiler fetch wave-uniform records and particles with scalar loads.
-template <bool kVec4, int kBlock, bool kPaper>
-__device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local, const uint4 *__restrict__ records,
+template <bool kVec4, int kBlock, bool kPaper, class Args>
+__device__ __forceinline__ void traverse_block(Args &a, int32_t local, const uint4 *__restrict__ records,
                                                const int32_t *__restrict__ ropes,
                                                const float4 *__restrict__ sorted,
                                                const uint4 *__restrict__ qpoint,
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const float4 *__restrict__ sorted, const uint4 *__restrict__ qpoint, const TreeMeta *__restrict__ meta) {
     __shared__ int32_t s_out[kRing][kBlock];
     __shared__ int32_t s_src[kBlock / 64][64];
-    traverse_block<kVec4, kBlock, kPaper>(a, xcd_logical_block(), records, ropes, sorted, qpoint, meta, s_out,
+    traverse_block<kVec4, kBlock, kPaper, const TravArgs>(a, xcd_logical_block(), records, ropes, sorted, qpoint, meta, s_out,
                                           s_src);
 }
 
@@ -367,13 +367,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     __shared__ int32_t s_src[kBlock / 64][64];
     const int32_t logical = xcd_logical_block();
     const int32_t sys = find_seg(tblk_first, nsys, logical);
-    traverse_block<kVec4, kBlock, false>(table[sys], logical - tblk_first[sys], records, ropes, sorted, nullptr,
+    // the system's arguments are read through the constant address space, as
+    // kernel arguments are: the compiler may then fetch a field again where it
+    // is needed instead of holding it in registers through the walk
+    using ConstArgs = const TravArgs __attribute__((address_space(4)));
+    ConstArgs *args = reinterpret_cast<ConstArgs *>(reinterpret_cast<uintptr_t>(table + sys));
+    traverse_block<kVec4, kBlock, false, ConstArgs>(*args, logical - tblk_first[sys], records, ropes, sorted, nullptr,
                                          meta_all + sys * QBVH_MAX_TYPES, s_out, s_src);
 }
 
 // One workgroup of queries: local workgroup `local` of the system `a`.
-template <bool kVec4, int kBlock, bool kPaper>
-__device__ __forceinline__ void traverse_block(const TravArgs &a, int32_t local, const uint4 *__restrict__ records,
+template <bool kVec4, int kBlock, bool kPaper, class Args>
+__device__ __forceinline__ void traverse_block(Args &a, int32_t local, const uint4 *__restrict__ records,
                                                const int32_t *__restrict__ ropes,
                                                const float4 *__restrict__ sorted,
                                                const uint4 *__restrict__ qpoint,
