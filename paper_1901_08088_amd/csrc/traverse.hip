@@ -329,7 +329,7 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, L
 // The read-only arrays come as separate __restrict__ parameters: that lets the
 // compiler fetch wave-uniform records and particles with scalar loads.
 template <bool kVec4, int kBlock, bool kPaper, class Args>
-__device__ __forceinline__ void traverse_block(Args &a, int32_t local, const uint4 *__restrict__ records,
+__device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 *__restrict__ records,
                                                const int32_t *__restrict__ ropes,
                                                const float4 *__restrict__ sorted,
                                                const uint4 *__restrict__ qpoint,
@@ -344,14 +344,42 @@ __device__ __forceinline__ int32_t xcd_logical_block() {
     return (int32_t)(xcd * qq + (xcd < rr ? xcd : rr) + (b >> 3));
 }
 
+// Systems of several types: the queries of each type are cut into eight
+// equal stretches, one per XCD, and every XCD takes its stretches in order
+// of increasing type size.  A sparse type's wavefronts span the widest
+// regions and run longest; this way they start first and are spread over all
+// XCDs instead of closing the launch on one.  The launch holds 8 ceil((ceil(n/8)
+// + ntypes) / kBlock) workgroups; returns a.n for a lane past its XCD's share.
+template <int kBlock>
+__device__ __forceinline__ int32_t balanced_query(const TravArgs &a, const TreeMeta *__restrict__ meta) {
+    const uint32_t xcd = blockIdx.x & 7u;
+    int32_t j = (int32_t)((blockIdx.x >> 3) * (uint32_t)kBlock + threadIdx.x);
+    for (int r = 0; r < a.ntypes; ++r) {
+        // the type of rank r by (count, type index)
+        int t = 0;
+        for (int u = 0; u < a.ntypes; ++u) {
+            int rank = 0;
+            for (int w = 0; w < a.ntypes; ++w)
+                rank += (meta[w].count < meta[u].count || (meta[w].count == meta[u].count && w < u)) ? 1 : 0;
+            if (rank == r) t = u;
+        }
+        const int64_t len = meta[t].count;
+        const int32_t lo = (int32_t)(len * xcd / 8), hi = (int32_t)(len * (xcd + 1) / 8);
+        if (j < hi - lo) return meta[t].start - a.start + lo + j;
+        j -= hi - lo;
+    }
+    return a.n;
+}
+
 template <bool kVec4, int kBlock, bool kPaper>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_traverse(
     TravArgs a, const uint4 *__restrict__ records, const int32_t *__restrict__ ropes,
     const float4 *__restrict__ sorted, const uint4 *__restrict__ qpoint, const TreeMeta *__restrict__ meta) {
     __shared__ int32_t s_out[kRing][kBlock];
     __shared__ int32_t s_src[kBlock / 64][64];
-    traverse_block<kVec4, kBlock, kPaper, const TravArgs>(a, xcd_logical_block(), records, ropes, sorted, qpoint, meta, s_out,
-                                          s_src);
+    const int32_t li = a.ntypes > 1 ? balanced_query<kBlock>(a, meta)
+                                    : xcd_logical_block() * kBlock + (int32_t)threadIdx.x;
+    traverse_block<kVec4, kBlock, kPaper, const TravArgs>(a, li, records, ropes, sorted, qpoint, meta, s_out, s_src);
 }
 
 // Batched form: the workgroups of all systems form one grid; each workgroup
@@ -372,20 +400,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     // is needed instead of holding it in registers through the walk
     using ConstArgs = const TravArgs __attribute__((address_space(4)));
     ConstArgs *args = reinterpret_cast<ConstArgs *>(reinterpret_cast<uintptr_t>(table + sys));
-    traverse_block<kVec4, kBlock, false, ConstArgs>(*args, logical - tblk_first[sys], records, ropes, sorted, nullptr,
-                                         meta_all + sys * QBVH_MAX_TYPES, s_out, s_src);
+    const int32_t li = (logical - tblk_first[sys]) * kBlock + (int32_t)threadIdx.x;
+    traverse_block<kVec4, kBlock, false, ConstArgs>(*args, li, records, ropes, sorted, nullptr,
+                                                    meta_all + sys * QBVH_MAX_TYPES, s_out, s_src);
 }
 
-// One workgroup of queries: local workgroup `local` of the system `a`.
+// One workgroup of queries; this lane's query is position `li` of the system
+// `a` (li >= a.n: an idle lane).
 template <bool kVec4, int kBlock, bool kPaper, class Args>
-__device__ __forceinline__ void traverse_block(Args &a, int32_t local, const uint4 *__restrict__ records,
+__device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 *__restrict__ records,
                                                const int32_t *__restrict__ ropes,
                                                const float4 *__restrict__ sorted,
                                                const uint4 *__restrict__ qpoint,
                                                const TreeMeta *__restrict__ meta, int32_t (*s_out)[kBlock],
                                                int32_t (*s_src_all)[64]) {
     int32_t *s_src = s_src_all[threadIdx.x >> 6];
-    const int32_t li = local * kBlock + (int32_t)threadIdx.x;
     const bool valid = li < a.n;  // idle lanes still take part in the shared walk
     const int32_t k = a.start + li;
     const uint32_t nend = (uint32_t)(a.start + a.n);
@@ -527,7 +556,10 @@ __global__ void k_clear_flag(int32_t *f) {
 
 template <bool kVec4, int kBlock, bool kPaper>
 void launch_one(const TravArgs &a, const uint4 *qpoint, hipStream_t s) {
-    const unsigned grid = (unsigned)((a.n + kBlock - 1) / kBlock);
+    // several types: the per-XCD stretches of balanced_query
+    const int64_t per_xcd = (a.n + 7) / 8 + a.ntypes;
+    const unsigned grid = a.ntypes > 1 ? (unsigned)(8 * ((per_xcd + kBlock - 1) / kBlock))
+                                       : (unsigned)((a.n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL((k_traverse<kVec4, kBlock, kPaper>), dim3(grid), dim3(kBlock), 0, s, a, a.records, a.ropes,
                        a.sorted, qpoint, a.meta);
 }
