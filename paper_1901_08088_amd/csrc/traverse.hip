@@ -140,33 +140,35 @@ __device__ __forceinline__ float4 particle(const char *__restrict__ base, uint32
 
 // fp32 pass over the particles of a run for every lane.  Accepts what is
 // surely in (d2 <= thr; thr = r2in for hitting lanes, -1 otherwise) and
-// counts in `nout` the pairs with d2 <= out (out = r2out for hitting lanes,
-// -1 otherwise); since thr <= out, some pair lies in the shell (thr, out]
-// that needs the exact test exactly when nout exceeds the accepted count.
-// The whole run (8 float4, padding included) is fetched with uniform loads
-// up front.  kSelf: the run may hold the lane's own particle at index `rel`,
-// which is never listed (nor counted in nout).
+// returns whether some lane has a pair in the shell (thr, out] (out = r2out
+// for hitting lanes, -1 otherwise), which then needs the exact test.  The
+// whole run (8 float4, padding included) is fetched with uniform loads up
+// front.  kSelf: the run may hold the lane's own particle at index `rel`,
+// which is never listed (nor taken as a shell pair).
 template <bool kSelf, int kBlock>
-__device__ __forceinline__ int32_t run_fp32(const char *__restrict__ base, uint32_t roff, uint32_t count, uint32_t rel,
-                                            float thr, float out, Lane &q, int32_t (*s_out)[kBlock]) {
+__device__ __forceinline__ bool run_fp32(const char *__restrict__ base, uint32_t roff, uint32_t count, uint32_t rel,
+                                         float thr, float out, Lane &q, int32_t (*s_out)[kBlock]) {
     float4 p[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) p[u] = particle(base, roff, (uint32_t)u);
     // both halves of the run are requested before the first test (the
     // compiler would otherwise delay the second load behind the early exits)
     asm volatile("" ::"s"(p[0].x), "s"(p[4].x));
-    int32_t nout = 0;
+    // lanes with a pair in the shell: the band masks are combined on the
+    // scalar unit, which leaves the VALU one compare per candidate for them
+    uint64_t band = 0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         if ((uint32_t)u >= count) break;
         const float ax = p[u].x - q.qsx, ay = p[u].y - q.qsy, az = p[u].z - q.qsz;
         const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
         const bool other = !kSelf || (uint32_t)u != rel;
+        const bool in = d2 <= thr && other;
         s_out[q.cnt & (kRing - 1)][threadIdx.x] = orig_of(p[u].w);
-        q.cnt += (d2 <= thr && other) ? 1 : 0;
-        nout += (d2 <= out && other) ? 1 : 0;
+        q.cnt += in ? 1 : 0;
+        band |= __ballot(d2 <= out && other) & ~__ballot(in);
     }
-    return nout;
+    return band != 0;
 }
 
 // Sparse runs.  When at most 8 lanes hit a run, testing every particle on
@@ -294,10 +296,8 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, L
             if (!self && sparse) {
                 shell = run_sparse<kBlock>(sbase, roff, c8, hit, hits, thr, out, q, s_out, s_src);
             } else {
-                const int32_t cnt0 = q.cnt;
-                const int32_t nout = self ? run_fp32<true, kBlock>(sbase, roff, c8, rel, thr, out, q, s_out)
-                                          : run_fp32<false, kBlock>(sbase, roff, c8, rel, thr, out, q, s_out);
-                shell = __any(nout != q.cnt - cnt0);
+                shell = self ? run_fp32<true, kBlock>(sbase, roff, c8, rel, thr, out, q, s_out)
+                             : run_fp32<false, kBlock>(sbase, roff, c8, rel, thr, out, q, s_out);
             }
             if (shell) {
                 // some pair lies in the shell around the cutoff: decide the
