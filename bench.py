@@ -77,13 +77,13 @@ def traversal_bytes(n: int, nrecords: int, stored_pairs: int) -> int:
 # factor the same counters read for a plain elementwise copy of known size (the
 # --copy-probe-mib kernel).  Valid only for the kernel sources it was taken on:
 # ``traffic`` is reported as null once their hash differs.
-TRAFFIC = {"sources": "989fe0bebfe1918f", "workload": "lj8m",
+TRAFFIC = {"sources": "bc979f7542a1710d", "workload": "lj8m",
            "opts": {"leaf_size": 16, "qbits": 16, "block_size": 128},
-           "fetch_kib": 1448174.79, "write_kib": 6571451.40, "copy_factor": 1.0,
-           "fetch_factor": 0.500022, "profile": "profiles/k_traverse_lj8m_counters.md",
+           "fetch_kib": 1490899.94, "write_kib": 6596541.92, "copy_factor": 1.0,
+           "fetch_factor": 0.500023, "profile": "profiles/k_traverse_lj8m_counters.md",
            # SQ_ACTIVE_INST_VALU / (SIMDs x kernel cycles / 4): the VALU issues one wave64
            # instruction per 4 cycles per SIMD, so this is the kernel's VALU issue roofline
-           "valu_busy": 0.94}
+           "valu_busy": 0.91}
 KERNEL_SOURCES = ("paper_1901_08088_amd/csrc/traverse.hip", "paper_1901_08088_amd/csrc/qbvh_internal.h")
 
 
