@@ -340,7 +340,7 @@ void fill_table(const BatchCtx &c, int32_t nsys, const qbvh_system_t *sys, const
         off += y.n;
         b += div_up(y.n, kBuildBlock);
         t += div_up(y.n, kTileItems);
-        tb += div_up(y.n, cfg.block);
+        tb += (int32_t)trav_blocks(y.n, y.ntypes, cfg.block);
     }
     sys_off[nsys] = off;
     blk[nsys] = b;
@@ -485,7 +485,7 @@ int run_many(int32_t nsys, const qbvh_system_t *sys, const qbvh_batch_opts_t *op
     e = ensure_capacity(*c, (int32_t)total, (int32_t)tiles, nsys);
     if (e != hipSuccess) return hip_fail(e);
     int64_t tblocks = 0;
-    for (int32_t s = 0; s < nsys; ++s) tblocks += div_up(sys[s].n, cfg.block);
+    for (int32_t s = 0; s < nsys; ++s) tblocks += trav_blocks(sys[s].n, sys[s].ntypes, cfg.block);
     std::vector<char> img;
     fill_table(*c, nsys, sys, trav, cfg, img);
     e = upload_table(*c, img);

@@ -125,6 +125,14 @@ struct BatchLaunch {
 };
 
 // Host helpers shared by the interface files.
+// Traversal workgroups of a system: a system of several types gets eight
+// equal stretches with room for an eighth of every type (see the traversal's
+// query order).
+inline int64_t trav_blocks(int64_t n, int32_t ntypes, int32_t block) {
+    if (ntypes <= 1) return (n + block - 1) / block;
+    return 8 * (((n + 7) / 8 + ntypes + block - 1) / block);
+}
+
 constexpr int32_t kMaxParticles = (1 << 27) - 1;  // particle runs store a sorted position in 27 bits
 inline bool leaf_ok(int32_t v) { return v >= 1 && v <= 16; }
 inline bool qbits_ok(int32_t v) { return v >= 8 && v <= 16; }

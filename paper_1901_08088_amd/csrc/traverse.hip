@@ -344,16 +344,22 @@ __device__ __forceinline__ int32_t xcd_logical_block() {
     return (int32_t)(xcd * qq + (xcd < rr ? xcd : rr) + (b >> 3));
 }
 
-// Systems of several types: the queries of each type are cut into eight
-// equal stretches, one per XCD, and every XCD takes its stretches in order
-// of increasing type size.  A sparse type's wavefronts span the widest
-// regions and run longest; this way they start first and are spread over all
-// XCDs instead of closing the launch on one.  The launch holds 8 ceil((ceil(n/8)
-// + ntypes) / kBlock) workgroups; returns a.n for a lane past its XCD's share.
-template <int kBlock>
-__device__ __forceinline__ int32_t balanced_query(const TravArgs &a, const TreeMeta *__restrict__ meta) {
-    const uint32_t xcd = blockIdx.x & 7u;
-    int32_t j = (int32_t)((blockIdx.x >> 3) * (uint32_t)kBlock + threadIdx.x);
+// Query order.  A system of one type takes its queries in sorted (Z) order.
+// In a system of several types, the workgroups form eight equal stretches
+// (one per XCD when the system covers the whole launch); stretch x takes the
+// x-th eighth of every type's queries, smallest type first.  A sparse type's
+// wavefronts span the widest regions and run longest: this way they start
+// first and are spread over the stretches instead of closing the launch on
+// one XCD.  `wg` is the system's workgroup in dispatch order and `nwg` its
+// workgroup count (trav_blocks); returns the lane's position in the system, or
+// a.n for a lane past its stretch's share.
+template <int kBlock, class Args>
+__device__ __forceinline__ int32_t query_position(Args &a, const TreeMeta *__restrict__ meta, int32_t wg,
+                                                  int32_t nwg) {
+    if (a.ntypes <= 1) return wg * kBlock + (int32_t)threadIdx.x;
+    const int32_t per = nwg / 8;
+    const int64_t part = wg / per;
+    int32_t j = (wg % per) * kBlock + (int32_t)threadIdx.x;
     for (int r = 0; r < a.ntypes; ++r) {
         // the type of rank r by (count, type index)
         int t = 0;
@@ -364,7 +370,7 @@ __device__ __forceinline__ int32_t balanced_query(const TravArgs &a, const TreeM
             if (rank == r) t = u;
         }
         const int64_t len = meta[t].count;
-        const int32_t lo = (int32_t)(len * xcd / 8), hi = (int32_t)(len * (xcd + 1) / 8);
+        const int32_t lo = (int32_t)(len * part / 8), hi = (int32_t)(len * (part + 1) / 8);
         if (j < hi - lo) return meta[t].start - a.start + lo + j;
         j -= hi - lo;
     }
@@ -377,8 +383,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const float4 *__restrict__ sorted, const uint4 *__restrict__ qpoint, const TreeMeta *__restrict__ meta) {
     __shared__ int32_t s_out[kRing][kBlock];
     __shared__ int32_t s_src[kBlock / 64][64];
-    const int32_t li = a.ntypes > 1 ? balanced_query<kBlock>(a, meta)
-                                    : xcd_logical_block() * kBlock + (int32_t)threadIdx.x;
+    const int32_t li = query_position<kBlock>(a, meta, xcd_logical_block(), (int32_t)gridDim.x);
     traverse_block<kVec4, kBlock, kPaper, const TravArgs>(a, li, records, ropes, sorted, qpoint, meta, s_out, s_src);
 }
 
@@ -400,9 +405,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     // is needed instead of holding it in registers through the walk
     using ConstArgs = const TravArgs __attribute__((address_space(4)));
     ConstArgs *args = reinterpret_cast<ConstArgs *>(reinterpret_cast<uintptr_t>(table + sys));
-    const int32_t li = (logical - tblk_first[sys]) * kBlock + (int32_t)threadIdx.x;
-    traverse_block<kVec4, kBlock, false, ConstArgs>(*args, li, records, ropes, sorted, nullptr,
-                                                    meta_all + sys * QBVH_MAX_TYPES, s_out, s_src);
+    const TreeMeta *meta = meta_all + sys * QBVH_MAX_TYPES;
+    const int32_t li = query_position<kBlock>(*args, meta, logical - tblk_first[sys], tblk_first[sys + 1] - tblk_first[sys]);
+    traverse_block<kVec4, kBlock, false, ConstArgs>(*args, li, records, ropes, sorted, nullptr, meta, s_out, s_src);
 }
 
 // One workgroup of queries; this lane's query is position `li` of the system
@@ -556,10 +561,7 @@ __global__ void k_clear_flag(int32_t *f) {
 
 template <bool kVec4, int kBlock, bool kPaper>
 void launch_one(const TravArgs &a, const uint4 *qpoint, hipStream_t s) {
-    // several types: the per-XCD stretches of balanced_query
-    const int64_t per_xcd = (a.n + 7) / 8 + a.ntypes;
-    const unsigned grid = a.ntypes > 1 ? (unsigned)(8 * ((per_xcd + kBlock - 1) / kBlock))
-                                       : (unsigned)((a.n + kBlock - 1) / kBlock);
+    const unsigned grid = (unsigned)trav_blocks(a.n, a.ntypes, kBlock);
     hipLaunchKernelGGL((k_traverse<kVec4, kBlock, kPaper>), dim3(grid), dim3(kBlock), 0, s, a, a.records, a.ropes,
                        a.sorted, qpoint, a.meta);
 }
