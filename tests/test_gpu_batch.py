@@ -20,8 +20,23 @@ def _mixed_systems():
                    rcut=np.array([[3.0]], np.float32), skin=0.4, name="single")
     empty = W.Config(pos=np.zeros((0, 3), np.float32), box=np.full(3, 10.0, np.float32),
                      rcut=np.array([[3.0]], np.float32), skin=0.4, name="empty")
-    cfgs += [one, empty]
+    empty2 = W.Config(pos=np.zeros((0, 3), np.float32), box=np.full(3, 10.0, np.float32),
+                      rcut=np.array([[1.0, 2.0], [2.0, 3.0]], np.float32), skin=0.4,
+                      types=np.zeros(0, np.int32), name="empty, two types")
+    cfgs += [one, empty, empty2, _four_types(37, seed=3)]
     return cfgs
+
+
+def _four_types(n, seed):
+    """Small four-type system: uneven type sizes, one type empty, two of equal size."""
+    pos, box = W.uniform(n, [12.0, 12.0, 12.0], seed=seed)
+    k = np.arange(n)
+    types = np.where(k % 9 == 0, 3, np.where(k % 9 == 1, 1, 0)).astype(np.int32)  # type 2 empty
+    if n >= 4:
+        types[-2:] = 1  # ties between counts become likely for small n
+    rcut = np.array([[1.5, 2.0, 1.0, 2.5], [2.0, 1.0, 0.0, 1.5], [1.0, 0.0, 2.0, 1.0], [2.5, 1.5, 1.0, 2.2]],
+                    np.float32)
+    return W.Config(pos=pos, box=box, rcut=rcut, skin=0.3, types=types, name=f"four types N={n}")
 
 
 def _check_all(cfgs, res, max_nbr, plain_counts=None):

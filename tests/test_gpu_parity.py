@@ -152,6 +152,24 @@ def test_disabled_type_pair_and_empty_type():
     compare_rows(cfg, nbr, cnt, ovf, 64)
 
 
+@pytest.mark.parametrize("n", [5, 37, 300, 5000])
+def test_four_types_uneven(n):
+    # several types: every type's queries are spread over eight stretches,
+    # smallest type first; types with fewer particles than stretches, an empty
+    # type and equal type sizes must still give every row exactly once
+    pos, box = W.uniform(n, [12.0, 12.0, 12.0], seed=n)
+    k = np.arange(n)
+    types = np.where(k % 9 == 0, 3, np.where(k % 9 == 1, 1, 0)).astype(np.int32)  # type 2 empty
+    if n >= 4:
+        types[-2:] = 1
+    rcut = np.array([[1.5, 2.0, 1.0, 2.5], [2.0, 1.0, 0.0, 1.5], [1.0, 0.0, 2.0, 1.0], [2.5, 1.5, 1.0, 2.2]],
+                    np.float32)
+    cfg = W.Config(pos=pos, box=box, rcut=rcut, skin=0.3, types=types)
+    for block in (64, 128, 256):
+        _, nbr, cnt, ovf = run_nlist(cfg, 64, opts={"leaf_size": 4, "block_size": block})
+        compare_rows(cfg, nbr, cnt, ovf, 64)
+
+
 def test_overflow_keeps_true_counts():
     cfg = W.lj_fluid(4000)
     _, nbr, cnt, ovf = run_nlist(cfg, 8)
