@@ -83,7 +83,7 @@ typedef struct {
     int32_t qbits;      /* grid bits per axis for the quantized bounds (8..16,
                            default 16; the paper's layout uses 10) */
     int32_t block_size; /* traversal workgroup size: 64, 128, 192 or 256
-                           (default 128) */
+                           (default 64) */
     int32_t validate;   /* 1: check every coordinate and type on the device and
                            wait for the result (the call then synchronizes the
                            stream); 0 (default): inputs are trusted */

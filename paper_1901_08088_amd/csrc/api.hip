@@ -31,7 +31,7 @@ int resolve_opts(const qbvh_opts_t *in, qbvh_opts_t *out) {
     if (in) o = *in;
     if (o.leaf_size == 0) o.leaf_size = 16;
     if (o.qbits == 0) o.qbits = 16;
-    if (o.block_size == 0) o.block_size = 128;
+    if (o.block_size == 0) o.block_size = 64;
     if (!qbi::leaf_ok(o.leaf_size) || !qbi::qbits_ok(o.qbits) || !qbi::block_ok(o.block_size)) return QBVH_EINVAL;
     if (o.validate != 0 && o.validate != 1) return QBVH_EINVAL;
     *out = o;

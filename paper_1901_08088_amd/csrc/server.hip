@@ -303,7 +303,7 @@ int qbvh_server_create(qbvh_server_t **srv, const qbvh_server_opts_t *opts) {
     if (o.max_inflight < 1 || o.max_inflight > 8 || o.max_batch < 1) return QBVH_EINVAL;
     if (o.batch.leaf_size == 0) o.batch.leaf_size = 16;
     if (o.batch.qbits == 0) o.batch.qbits = 16;
-    if (o.batch.block_size == 0) o.batch.block_size = 128;
+    if (o.batch.block_size == 0) o.batch.block_size = 64;
     o.batch.eager = 1;
     if (!qbi::leaf_ok(o.batch.leaf_size) || !qbi::qbits_ok(o.batch.qbits) || !qbi::block_ok(o.batch.block_size))
         return QBVH_EINVAL;
