@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 import workloads as W  # noqa: E402
 
 import hashlib  # noqa: E402
+import re  # noqa: E402
 
 METRIC = "nlist builds/s & pairs/s at 1 GPU vs oracle; batched vs plain; HBM GB/s %"
 HBM_PEAK_GBS = 8000.0
@@ -77,7 +78,7 @@ def traversal_bytes(n: int, nrecords: int, stored_pairs: int) -> int:
 # factor the same counters read for a plain elementwise copy of known size (the
 # --copy-probe-mib kernel).  Valid only for the kernel sources it was taken on:
 # ``traffic`` is reported as null once their hash differs.
-TRAFFIC = {"sources": "059235e17e539da6", "workload": "lj8m",
+TRAFFIC = {"sources": "652deee8202b3cf7", "workload": "lj8m",
            "opts": {"leaf_size": 16, "qbits": 16, "block_size": 64},
            "fetch_kib": 1540595.48, "write_kib": 6605464.07, "copy_factor": 1.0,
            "fetch_factor": 0.500023, "profile": "profiles/k_traverse_lj8m_counters.md",
@@ -87,11 +88,20 @@ TRAFFIC = {"sources": "059235e17e539da6", "workload": "lj8m",
 KERNEL_SOURCES = ("paper_1901_08088_amd/csrc/traverse.hip", "paper_1901_08088_amd/csrc/qbvh_internal.h")
 
 
+def _code_only(text: str) -> str:
+    """The source with comments and blank space removed: a comment edit does not
+    change the kernel the counters were taken on.  (No string literal in these
+    sources holds a comment marker.)"""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

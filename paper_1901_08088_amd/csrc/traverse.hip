@@ -5,7 +5,7 @@
 //
 // Per wavefront and per type tree:
 //   1. image mask per lane: which of the 27 periodic images of its search
-//      sphere touch the tree's root box (Algorithm 1, line 4); the wavefront
+//      sphere touch the tree's root box (the image test of Algorithm 1); the wavefront
 //      visits the union of its lanes' images;
 //   2. per image, one stackless walk over the two-wide records, shared by the
 //      wavefront.  A step loads one record (both child boxes and references)
@@ -448,7 +448,7 @@ __device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 
         q.r2 = r2;
         const double R = lane_on ? sqrt(r2) : 0.0;
 
-        // (1) image mask against the root box (Algorithm 1, line 4), in fp32
+        // (1) image mask against the root box (the image test of Algorithm 1), in fp32
         // with an outward pad of 2^-18 of the largest box edge (far above the
         // fp32 rounding of the shifted coordinates) plus 2^-20 relative.
         uint32_t bits = 0;
@@ -494,7 +494,7 @@ __device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 
             q.rp2 = (float)(rp * rp * (1.0 + 0x1p-20));
         }
 
-        // (2) one shared stackless walk per image in the union (Algorithm 1, lines 5-19)
+        // (2) one shared stackless walk per image in the union (the walk of Algorithm 1)
         while (wave_bits) {
             const int img = __builtin_ctz(wave_bits);
             wave_bits &= wave_bits - 1u;
