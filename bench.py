@@ -395,8 +395,8 @@ def main(argv=None) -> int:
                     help="after timing, run a plain copy kernel of this size (counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py: runs on one GPU only; --gpus must be 1 "
+              "(multi-GPU sharding is not implemented)", file=sys.stderr)
         return 2
 
     import torch

@@ -69,7 +69,7 @@ enum {
     QBVH_ENOMEM = -3, /* device allocation failed */
     QBVH_EHIP = -4,   /* a HIP runtime call failed; qbvh_last_hip_error() has it */
     QBVH_EAGAIN = -5, /* server admission: the request does not fit right now */
-    QBVH_ENOTSUP = -6 /* valid request this build does not support */
+    QBVH_ENOTSUP = -6 /* valid request the library does not support */
 };
 
 #define QBVH_MAX_TYPES 4
