@@ -200,6 +200,7 @@ int nlist_build_ex(const qbvh_t *tree, const float *rcut, float skin, int32_t ma
     a.n = tree->n;
     a.ntypes = tree->ntypes;
     a.max_nbr = max_nbr;
+    a.qpw = qbi::queries_per_wave(tree->n);
     const bool vec4 = max_nbr > 0 && (max_nbr % 4) == 0 && (((uintptr_t)d_nbr) & 15u) == 0;
     const bool paper = mode == QBVH_LIST_PAPER;
     hipStream_t s = (hipStream_t)stream;

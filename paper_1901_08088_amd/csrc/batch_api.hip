@@ -336,6 +336,7 @@ void fill_table(const BatchCtx &c, int32_t nsys, const qbvh_system_t *sys, const
         a.sorted = c.ws.sorted;
         a.meta = meta_dev + (size_t)s * QBVH_MAX_TYPES;
         a.start = off;
+        a.qpw = 64;  // a batch fills the GPU with many systems' wavefronts
         ta[s] = a;
         off += y.n;
         b += div_up(y.n, kBuildBlock);

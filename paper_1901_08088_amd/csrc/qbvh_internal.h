@@ -92,6 +92,8 @@ struct TravArgs {
     int32_t ntypes;
     int32_t max_nbr;
     int32_t start;    // first sorted position of this system (0 for a single system)
+    int32_t qpw;      // queries per wavefront (64, or 32/16/8 for small systems)
+    int32_t pad1;
 };
 
 // One system of a batch as the build kernels see it.
@@ -125,12 +127,24 @@ struct BatchLaunch {
 };
 
 // Host helpers shared by the interface files.
-// Traversal workgroups of a system: a system of several types gets eight
-// equal stretches with room for an eighth of every type (see the traversal's
-// query order).
-inline int64_t trav_blocks(int64_t n, int32_t ntypes, int32_t block) {
-    if (ntypes <= 1) return (n + block - 1) / block;
-    return 8 * (((n + 7) / 8 + ntypes + block - 1) / block);
+// Traversal workgroups of a system whose wavefronts take `qpw` queries each: a
+// system of several types gets eight equal stretches with room for an eighth
+// of every type (see the traversal's query order).
+inline int64_t trav_blocks(int64_t n, int32_t ntypes, int32_t block, int32_t qpw = 64) {
+    const int64_t per_wg = (int64_t)(block / 64) * qpw;
+    if (ntypes <= 1) return (n + per_wg - 1) / per_wg;
+    return 8 * (((n + 7) / 8 + ntypes + per_wg - 1) / per_wg);
+}
+
+// Queries per wavefront of a single system.  A wavefront walks the union of
+// its queries' paths, so a small system is faster with fewer queries per
+// wavefront (a smaller union each, more wavefronts in parallel) as long as the
+// wavefronts do not outnumber the 1024 SIMDs; a large one keeps all 64 lanes
+// busy.
+inline int32_t queries_per_wave(int64_t n) {
+    int32_t q = 64;
+    while (q > 8 && (n + q - 1) / q < 1024) q /= 2;
+    return q;
 }
 
 constexpr int32_t kMaxParticles = (1 << 27) - 1;  // particle runs store a sorted position in 27 bits

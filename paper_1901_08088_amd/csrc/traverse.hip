@@ -356,10 +356,13 @@ __device__ __forceinline__ int32_t xcd_logical_block() {
 template <int kBlock, class Args>
 __device__ __forceinline__ int32_t query_position(Args &a, const TreeMeta *__restrict__ meta, int32_t wg,
                                                   int32_t nwg) {
-    if (a.ntypes <= 1) return wg * kBlock + (int32_t)threadIdx.x;
+    // wavefronts of a.qpw queries: lanes past a.qpw idle
+    const int32_t qpw = a.qpw, lane = (int32_t)(threadIdx.x & 63u), wave = (int32_t)(threadIdx.x >> 6);
+    if (lane >= qpw) return a.n;
+    if (a.ntypes <= 1) return (wg * (kBlock / 64) + wave) * qpw + lane;
     const int32_t per = nwg / 8;
     const int64_t part = wg / per;
-    int32_t j = (wg % per) * kBlock + (int32_t)threadIdx.x;
+    int32_t j = ((wg % per) * (kBlock / 64) + wave) * qpw + lane;
     for (int r = 0; r < a.ntypes; ++r) {
         // the type of rank r by (count, type index)
         int t = 0;
@@ -561,7 +564,7 @@ __global__ void k_clear_flag(int32_t *f) {
 
 template <bool kVec4, int kBlock, bool kPaper>
 void launch_one(const TravArgs &a, const uint4 *qpoint, hipStream_t s) {
-    const unsigned grid = (unsigned)trav_blocks(a.n, a.ntypes, kBlock);
+    const unsigned grid = (unsigned)trav_blocks(a.n, a.ntypes, kBlock, a.qpw);
     hipLaunchKernelGGL((k_traverse<kVec4, kBlock, kPaper>), dim3(grid), dim3(kBlock), 0, s, a, a.records, a.ropes,
                        a.sorted, qpoint, a.meta);
 }
