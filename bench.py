@@ -78,10 +78,10 @@ def traversal_bytes(n: int, nrecords: int, stored_pairs: int) -> int:
 # factor the same counters read for a plain elementwise copy of known size (the
 # --copy-probe-mib kernel).  Valid only for the kernel sources it was taken on:
 # ``traffic`` is reported as null once their hash differs.
-TRAFFIC = {"sources": "652deee8202b3cf7", "workload": "lj8m",
+TRAFFIC = {"sources": "02eae8707c3ef86a", "workload": "lj8m",
            "opts": {"leaf_size": 16, "qbits": 16, "block_size": 64},
-           "fetch_kib": 1540595.48, "write_kib": 6605464.07, "copy_factor": 1.0,
-           "fetch_factor": 0.500023, "profile": "profiles/k_traverse_lj8m_counters.md",
+           "fetch_kib": 1591920.63, "write_kib": 6643493.78, "copy_factor": 1.0,
+           "fetch_factor": 0.500024, "profile": "profiles/k_traverse_lj8m_counters.md",
            # SQ_ACTIVE_INST_VALU / (SIMDs x kernel cycles / 4): the VALU issues one wave64
            # instruction per 4 cycles per SIMD, so this is the kernel's VALU issue roofline
            "valu_busy": 0.92}

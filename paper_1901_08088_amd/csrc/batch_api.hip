@@ -301,7 +301,7 @@ void destroy_ctx(BatchCtx *c) {
 
 // Host image of the uploaded part of the table for configuration `cfg`.
 void fill_table(const BatchCtx &c, int32_t nsys, const qbvh_system_t *sys, const std::vector<TravArgs> &trav,
-                const Cfg &cfg, std::vector<char> &img) {
+                const Cfg &cfg, int32_t qpw, std::vector<char> &img) {
     const TabLayout lay(c.cap_nsys);
     img.assign(lay.upload, 0);
     int32_t *sys_off = (int32_t *)(img.data() + lay.sys_off);
@@ -336,12 +336,12 @@ void fill_table(const BatchCtx &c, int32_t nsys, const qbvh_system_t *sys, const
         a.sorted = c.ws.sorted;
         a.meta = meta_dev + (size_t)s * QBVH_MAX_TYPES;
         a.start = off;
-        a.qpw = 64;  // a batch fills the GPU with many systems' wavefronts
+        a.qpw = qpw;
         ta[s] = a;
         off += y.n;
         b += div_up(y.n, kBuildBlock);
         t += div_up(y.n, kTileItems);
-        tb += (int32_t)trav_blocks(y.n, y.ntypes, cfg.block);
+        tb += (int32_t)trav_blocks(y.n, y.ntypes, cfg.block, qpw);
     }
     sys_off[nsys] = off;
     blk[nsys] = b;
@@ -485,10 +485,13 @@ int run_many(int32_t nsys, const qbvh_system_t *sys, const qbvh_batch_opts_t *op
 
     e = ensure_capacity(*c, (int32_t)total, (int32_t)tiles, nsys);
     if (e != hipSuccess) return hip_fail(e);
+    // queries per wavefront from the batch's total: a batch of many systems
+    // fills the GPU with 64-query wavefronts, a small one gets smaller ones
+    const int32_t qpw = queries_per_wave(total);
     int64_t tblocks = 0;
-    for (int32_t s = 0; s < nsys; ++s) tblocks += trav_blocks(sys[s].n, sys[s].ntypes, cfg.block);
+    for (int32_t s = 0; s < nsys; ++s) tblocks += trav_blocks(sys[s].n, sys[s].ntypes, cfg.block, qpw);
     std::vector<char> img;
-    fill_table(*c, nsys, sys, trav, cfg, img);
+    fill_table(*c, nsys, sys, trav, cfg, qpw, img);
     e = upload_table(*c, img);
     if (e != hipSuccess) return hip_fail(e);
     const BatchLaunch b =
