@@ -118,8 +118,9 @@ def test_lj4000_options(opts):
     compare_rows(cfg, nbr, cnt, ovf, 256)
 
 
-@pytest.mark.parametrize("n,rho", [(50, 0.05), (777, 0.3), (12411, 0.85), (30000, 0.6)])
+@pytest.mark.parametrize("n,rho", [(50, 0.05), (777, 0.3), (12411, 0.85), (30000, 0.6), (40000, 0.85)])
 def test_lattice_fluids(n, rho):
+    # 50 to 30000 particles run 8 queries per wavefront, 40000 runs 16
     cfg = W.lj_fluid(n, seed=n, rho=rho)
     if 2 * 3.4 >= cfg.box.min():
         cfg = W.lj_fluid(n, seed=n, rho=rho, rc=1.0, skin=0.2)
