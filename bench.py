@@ -41,12 +41,19 @@ WORKLOADS = {
     "lj4000": dict(n=4000, rho=0.85, rc=3.0, skin=0.4, max_nbr=256),
     # two-type colloid/solvent mixture (one tree per type), 2% colloids of diameter 5
     "colloid1m": dict(n=1_000_000, kind="colloid", skin=0.4, max_nbr=256),
+    # WCA short cutoff (rc = 2^(1/6)) and a spinodal-like liquid (0.75) / vapor (0.05) structure
+    "wca1m": dict(n=1_000_000, kind="wca", rho=0.85, skin=0.4, max_nbr=64),
+    "spinodal1m": dict(n=1_000_000, kind="spinodal", skin=0.4, max_nbr=256),
 }
 
 
 def make_config(wl: dict):
     if wl.get("kind") == "colloid":
         return W.colloid_solvent(wl["n"], skin=wl["skin"])
+    if wl.get("kind") == "wca":
+        return W.wca_fluid(wl["n"], rho=wl["rho"], skin=wl["skin"])
+    if wl.get("kind") == "spinodal":
+        return W.spinodal(wl["n"], skin=wl["skin"])
     return W.lj_fluid(wl["n"], rho=wl["rho"], rc=wl["rc"], skin=wl["skin"])
 
 
@@ -57,6 +64,13 @@ def describe(wl: dict, cfg) -> str:
                 f"L={m['L']:.2f}, colloid volume fraction {m['colloid_volume_fraction']:.3f}) rc_ij=(d_i+d_j)/2 "
                 f"skin={wl['skin']} max_nbr={wl['max_nbr']} fp32, one tree per type (RSA placement, seed "
                 f"{m['seed']})")
+    if wl.get("kind") == "wca":
+        return (f"wca_fluid N={cfg.n:,} rho={wl['rho']} rc=2^(1/6) skin={wl['skin']} max_nbr={wl['max_nbr']} "
+                f"fp32 (jittered simple-cubic lattice, seed {cfg.meta['seed']})")
+    if wl.get("kind") == "spinodal":
+        m = cfg.meta
+        return (f"spinodal N={cfg.n:,} (liquid 0.75 / vapor 0.05 bicontinuous domains of {m['wavelength']:g} sigma, "
+                f"L={m['L']:.2f}) rc=3.0 skin={wl['skin']} max_nbr={wl['max_nbr']} fp32 (seed {m['seed']})")
     return (f"lj_fluid N={cfg.n:,} rho={wl['rho']} rc={wl['rc']} skin={wl['skin']} "
             f"max_nbr={wl['max_nbr']} fp32 (jittered simple-cubic lattice, seed {cfg.meta['seed']})")
 

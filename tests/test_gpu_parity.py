@@ -128,6 +128,20 @@ def test_lattice_fluids(n, rho):
     compare_rows(cfg, nbr, cnt, ovf, 256)
 
 
+def test_wca_fluid_rows():
+    # short cutoff (rc = 2^(1/6)): about a dozen neighbors, small leaf boxes
+    cfg = W.wca_fluid(30000)
+    _, nbr, cnt, ovf = run_nlist(cfg, 64)
+    compare_rows(cfg, nbr, cnt, ovf, 64)
+
+
+def test_spinodal_rows():
+    # liquid (0.75) and vapor (0.05) domains: wavefronts of very different work
+    cfg = W.spinodal(30000)
+    _, nbr, cnt, ovf = run_nlist(cfg, 256)
+    compare_rows(cfg, nbr, cnt, ovf, 256)
+
+
 def test_uniform_noncubic_box_scalar_rows():
     pos, box = W.uniform(9000, [17.0, 23.0, 29.0], seed=4)
     cfg = W.Config(pos=pos, box=box, rcut=np.array([[2.5]], np.float32), skin=0.3)

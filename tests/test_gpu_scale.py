@@ -1,7 +1,8 @@
 """Parity at the full sizes of the Lennard-Jones workloads (N = 1M and 8M,
-density 0.85, rc 3.0 + skin 0.4, max_nbr 256), in the launch configuration the
-benchmark times: every count against the oracle's cell list, and complete rows
-for a seeded sample of particles."""
+density 0.85, rc 3.0 + skin 0.4, max_nbr 256), of the 1M WCA fluid (short
+cutoff) and of the 1M spinodal-like liquid-vapor configuration, in the launch
+configuration the benchmark times: every count against the oracle's cell list,
+and complete rows for a seeded sample of particles."""
 import numpy as np
 import pytest
 
@@ -16,11 +17,13 @@ pytestmark = pytest.mark.gpu
 from bench import BENCH_OPTS  # the launch configuration bench.py times
 
 
-@pytest.mark.parametrize("n", [1_000_000, 8_000_000])
-def test_lj_fluid_full_size(n):
+@pytest.mark.parametrize("n,kind", [(1_000_000, "lj"), (8_000_000, "lj"), (1_000_000, "wca"),
+                                    (1_000_000, "spinodal")])
+def test_lj_fluid_full_size(n, kind):
     torch = require_gpu()
-    cfg = W.lj_fluid(n)
-    print(f"[scale] N={n} L={cfg.box[0]:.4f}", flush=True)
+    cfg = {"lj": W.lj_fluid, "wca": W.wca_fluid, "spinodal": W.spinodal}[kind](n)
+    n = cfg.n
+    print(f"[scale] {kind} N={n} L={cfg.box[0]:.4f}", flush=True)
     pos = torch.from_numpy(cfg.pos).cuda()
     tree = Q.qbvh_build(pos, None, cfg.box, 1, BENCH_OPTS)
     max_nbr = 256
@@ -43,4 +46,4 @@ def test_lj_fluid_full_size(n):
     for q, i in enumerate(sample):
         c = gcnt[i]
         assert sorted(rows[q, :c].tolist()) == cols[rp[q]:rp[q + 1]].tolist(), i
-    print(f"[scale] N={n} pairs={int(gcnt.sum())} mean={gcnt.mean():.3f} ok", flush=True)
+    print(f"[scale] {kind} N={n} pairs={int(gcnt.sum())} mean={gcnt.mean():.3f} ok", flush=True)

@@ -55,3 +55,23 @@ def test_mixture_recipe_small():
     c = W.colloid_solvent(n_total=3000, seed=7)
     _valid(c)
     assert c.ntypes == 2 and int((c.types == 1).sum()) == 60
+
+
+def test_wca_fluid_recipe():
+    c = W.wca_fluid(4000)
+    _valid(c)
+    assert abs(float(c.rcut[0, 0]) - 2.0 ** (1.0 / 6.0)) < 1e-6
+    assert np.array_equal(c.pos, W.wca_fluid(4000).pos)  # seeded
+
+
+@pytest.mark.parametrize("n", [30_000, 200_000])
+def test_spinodal_recipe(n):
+    c = W.spinodal(n)
+    _valid(c)
+    assert abs(c.n - n) < 0.1 * n
+    m = c.meta
+    # liquid and vapor each fill about half of the box
+    v_half = 0.5 * m["L"] ** 3
+    assert abs(m["n_liquid"] / v_half - 0.75) < 0.08
+    assert abs(m["n_vapor"] / v_half - 0.05) < 0.01
+    assert np.array_equal(c.pos, W.spinodal(n).pos)  # seeded

@@ -40,6 +40,8 @@ SEEDS = {
     "colloid": 19010884,
     "ensemble": 19010885,
     "served": 19010886,
+    "wca": 19010887,
+    "spinodal": 19010888,
 }
 
 
@@ -276,6 +278,65 @@ def ensemble(n_systems: int = 256, seed=SEEDS["ensemble"], n_min: int = 2000, n_
         out.append(Config(pos=pos, box=box, rcut=np.array([[rc]], dtype=np.float32), skin=skin,
                           name=f"replica{k}_N{n}", meta={"rho": rho, "rc": rc, "index": k}))
     return out
+
+
+WCA_RC = 2.0 ** (1.0 / 6.0)
+
+
+def wca_fluid(n_particles: int, seed=SEEDS["wca"], rho: float = 0.85, skin: float = 0.4) -> Config:
+    """Purely repulsive (WCA) fluid stand-in: the LJ lattice generator with the
+    short cutoff rc = 2^(1/6) sigma, so each particle has only ~12 list
+    neighbors (the low-occupancy case the paper names as hard for grids)."""
+    pos, box = lj_lattice(n_particles, rho, seed)
+    return Config(pos=pos, box=box, rcut=np.array([[WCA_RC]], dtype=np.float32), skin=skin,
+                  name=f"wca_fluid_N{n_particles}_rho{rho}", meta={"rho": rho, "seed": seed})
+
+
+def _bicontinuous_field(rng, box64: np.ndarray, n_modes: int, wavelength: float):
+    """A smooth random field on the periodic box: a sum of plane waves whose
+    wavevectors are lattice vectors of the box with length near 2 pi / wavelength."""
+    m_max = np.maximum(1, np.round(box64 / wavelength * 1.5)).astype(int)
+    cand = np.stack(np.meshgrid(*[np.arange(-m, m + 1) for m in m_max], indexing="ij"), -1).reshape(-1, 3)
+    k = 2.0 * np.pi * cand / box64
+    kn = np.linalg.norm(k, axis=1)
+    k0 = 2.0 * np.pi / wavelength
+    pool = np.nonzero(np.abs(kn - k0) <= 0.35 * k0)[0]
+    pick = rng.choice(pool, size=min(n_modes, pool.size), replace=False)
+    kv, phase = k[pick], rng.uniform(0.0, 2.0 * np.pi, size=pick.size)
+
+    def field(x):
+        return np.cos(x @ kv.T + phase).sum(axis=1)
+    return field
+
+
+def spinodal(n_target: int = 1_000_000, seed=SEEDS["spinodal"], rho_liquid: float = 0.75,
+             rho_vapor: float = 0.05, wavelength: float = 30.0, rc: float = 3.0, skin: float = 0.4) -> Config:
+    """Spinodal-like liquid-vapor configuration: a bicontinuous structure in
+    which half of the box (where a smooth random field of domain size
+    ``wavelength`` is positive) holds liquid at ``rho_liquid`` (jittered cubic
+    lattice, kept where the field is positive) and the other half holds vapor
+    at ``rho_vapor`` (uniform points, kept where it is negative).  This is the
+    strong density variation the paper's spinodal benchmarks show; the box is
+    cubic with L chosen so that about ``n_target`` particles result."""
+    rng = np.random.default_rng(seed)
+    L = (n_target / (0.5 * (rho_liquid + rho_vapor))) ** (1.0 / 3.0)
+    box32 = np.full(3, L, dtype=np.float32)
+    box64 = box32.astype(np.float64)
+    field = _bicontinuous_field(rng, box64, 24, wavelength)
+    n = int(np.ceil((rho_liquid * box64.prod()) ** (1.0 / 3.0)))
+    a = box64 / n
+    g = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)
+    liq = (g + 0.5) * a + rng.uniform(-0.3, 0.3, size=g.shape) * a
+    liq = liq[field(liq) > 0.0]
+    n_vap = int(round(rho_vapor * box64.prod()))
+    vap = rng.uniform(0.0, 1.0, size=(4 * n_vap + 64, 3)) * box64
+    vap = vap[field(vap) <= 0.0][: n_vap // 2]
+    pos64 = np.concatenate([liq, vap], axis=0)
+    pos64 = pos64[rng.permutation(pos64.shape[0])]
+    return Config(pos=wrap_f32(pos64, box32), box=box32, rcut=np.array([[rc]], dtype=np.float32), skin=skin,
+                  name=f"spinodal_N{pos64.shape[0]}",
+                  meta={"seed": seed, "n_liquid": int(liq.shape[0]), "n_vapor": int(vap.shape[0]),
+                        "L": float(L), "wavelength": wavelength})
 
 
 def slab(n_target_liquid_thickness: float = 80.0, seed=SEEDS["served"], box=(60.0, 60.0, 240.0),
