@@ -86,9 +86,19 @@ def max_threads() -> int:
     return int(_load().oracle_max_threads())
 
 
+def _as_f64(pos, box):
+    """Positions and box as fp64.  fp32 data (the default) is converted exactly;
+    fp64 positions keep their values and take the box as given in fp64."""
+    pos = np.asarray(pos)
+    if pos.dtype == np.float64:
+        return (np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3),
+                np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(3)))
+    return (np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3).astype(np.float64),
+            np.ascontiguousarray(np.asarray(box, dtype=np.float32).astype(np.float64).reshape(3)))
+
+
 def _prep(pos, box, rcut, skin, types):
-    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
-    box = np.ascontiguousarray(np.asarray(box, dtype=np.float32).astype(np.float64).reshape(3))
+    pos, box = _as_f64(pos, box)
     r2 = np.ascontiguousarray(rlist2_table(rcut, skin))
     ntypes = r2.shape[0]
     t = None if types is None else np.ascontiguousarray(types, dtype=np.int32)
@@ -158,22 +168,22 @@ def neighbor_counts(pos, box, rcut, skin, types=None, queries=None, method: str 
 
 
 def pair_d2(pi, pj, box) -> float:
-    """fp64 minimum-image squared distance of two fp32 points, same arithmetic as the lists."""
+    """fp64 minimum-image squared distance of two points (fp32, or fp64 with an
+    fp64 box), same arithmetic as the lists."""
     lib = _load()
-    a = np.ascontiguousarray(pi, dtype=np.float32).reshape(3)
-    b = np.ascontiguousarray(pj, dtype=np.float32).reshape(3)
-    L = np.ascontiguousarray(np.asarray(box, dtype=np.float32).astype(np.float64).reshape(3))
+    ab, L = _as_f64(np.stack([np.asarray(pi), np.asarray(pj)]), box)
+    a = np.ascontiguousarray(ab[0])
+    b = np.ascontiguousarray(ab[1])
     return float(lib.oracle_pair_d2(_ptr(a), _ptr(b), _ptr(L)))
 
 
 def band_pairs(pos, box, rcut, skin, row_ptr, cols, queries=None, types=None, rel: float = 1e-5):
     """Number of listed pairs whose distance lies within ``rel * r_list`` of the list radius."""
-    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
-    L = np.asarray(box, dtype=np.float32).astype(np.float64)
+    pos, L = _as_f64(pos, box)
     r2 = rlist2_table(rcut, skin)
     qi = np.arange(row_ptr.shape[0] - 1) if queries is None else np.asarray(queries)
     rows = np.repeat(qi, np.diff(row_ptr))
-    d = pos[cols].astype(np.float64) - pos[rows].astype(np.float64)
+    d = pos[cols] - pos[rows]
     d = d - L * np.round(d / L)
     dist = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
     ti = np.zeros(rows.shape[0], np.int64) if types is None else np.asarray(types)[rows]

@@ -14,9 +14,10 @@
  *   d_ij^2 = (dx_0*dx_0 + dx_1*dx_1) + dx_2*dx_2
  *   dx_d   = (x_j,d - x_i,d) - L_d * round((x_j,d - x_i,d) / L_d)
  *
- * All arithmetic is IEEE fp64 on the exactly converted fp32 inputs, in the
- * order written above, with no contraction into fused multiply-adds (build
- * with -ffp-contract=off).  r_list^2 is supplied by the caller per type pair;
+ * All arithmetic is IEEE fp64, in the order written above, with no
+ * contraction into fused multiply-adds (build with -ffp-contract=off).
+ * Positions come in as fp64: fp32 data converted exactly (the paper's fp32
+ * case), or fp64 data as given (its fp64 case, Section 2.2 and Figs. 4-7).  r_list^2 is supplied by the caller per type pair;
  * a negative value means the pair of types is never listed.
  *
  * Two independent ways to evaluate S_i:
@@ -34,7 +35,7 @@
 #include <omp.h>
 #endif
 
-static double pair_d2(const float *pi, const float *pj, const double *L)
+static double pair_d2(const double *pi, const double *pj, const double *L)
 {
     double dx[3];
     for (int d = 0; d < 3; ++d) {
@@ -71,7 +72,7 @@ int oracle_max_threads(void)
 /* ---------------------------------------------------------------- brute force */
 
 /* count[q] = |S_{queries[q]}| (queries == NULL means all particles). */
-int oracle_count_brute(int64_t n, const float *pos, const int32_t *type, int32_t ntypes,
+int oracle_count_brute(int64_t n, const double *pos, const int32_t *type, int32_t ntypes,
                        const double *box, const double *rlist2, int64_t nq,
                        const int64_t *queries, int64_t *count, int nthreads)
 {
@@ -96,7 +97,7 @@ int oracle_count_brute(int64_t n, const float *pos, const int32_t *type, int32_t
 }
 
 /* Fill rows: row q occupies cols[row_ptr[q] .. row_ptr[q+1]). */
-int oracle_fill_brute(int64_t n, const float *pos, const int32_t *type, int32_t ntypes,
+int oracle_fill_brute(int64_t n, const double *pos, const int32_t *type, int32_t ntypes,
                       const double *box, const double *rlist2, int64_t nq,
                       const int64_t *queries, const int64_t *row_ptr, int32_t *cols,
                       int nthreads)
@@ -139,7 +140,7 @@ static int64_t cell_coord(double x, double w, int64_t nc)
     return (int64_t)c;
 }
 
-static int64_t cell_of(const cells_t *g, const float *p)
+static int64_t cell_of(const cells_t *g, const double *p)
 {
     int64_t c0 = cell_coord((double)p[0], g->width[0], g->nc[0]);
     int64_t c1 = cell_coord((double)p[1], g->width[1], g->nc[1]);
@@ -151,7 +152,7 @@ static int64_t cell_of(const cells_t *g, const float *p)
  * other (minimum image) sit in cells whose coordinates differ by at most one,
  * modulo the cell count.  Returns 0 when fewer than 3 cells fit on an axis
  * (the 27 stencil cells would then not be distinct). */
-static int cells_build(cells_t *g, int64_t n, const float *pos, const double *box, double rmax)
+static int cells_build(cells_t *g, int64_t n, const double *pos, const double *box, double rmax)
 {
     memset(g, 0, sizeof(*g));
     for (int d = 0; d < 3; ++d) {
@@ -212,7 +213,7 @@ static int cmp_i32(const void *a, const void *b)
 }
 
 /* Visit the 27 stencil cells of particle i; count or store its neighbors. */
-static int64_t cells_row(const cells_t *g, int64_t i, const float *pos, const int32_t *type,
+static int64_t cells_row(const cells_t *g, int64_t i, const double *pos, const int32_t *type,
                          int32_t ntypes, const double *box, const double *rlist2, int32_t *out)
 {
     int64_t c0 = cell_coord((double)pos[3 * i + 0], g->width[0], g->nc[0]);
@@ -257,7 +258,7 @@ static double max_radius(int32_t ntypes, const double *rlist2)
 
 /* Returns 0 on success, 1 when the box is too small for a 3x3x3 stencil
  * (the caller then uses the brute-force functions), -1 on error. */
-int oracle_count_cells(int64_t n, const float *pos, const int32_t *type, int32_t ntypes,
+int oracle_count_cells(int64_t n, const double *pos, const int32_t *type, int32_t ntypes,
                        const double *box, const double *rlist2, int64_t nq,
                        const int64_t *queries, int64_t *count, int nthreads)
 {
@@ -277,7 +278,7 @@ int oracle_count_cells(int64_t n, const float *pos, const int32_t *type, int32_t
     return 0;
 }
 
-int oracle_fill_cells(int64_t n, const float *pos, const int32_t *type, int32_t ntypes,
+int oracle_fill_cells(int64_t n, const double *pos, const int32_t *type, int32_t ntypes,
                       const double *box, const double *rlist2, int64_t nq,
                       const int64_t *queries, const int64_t *row_ptr, int32_t *cols,
                       int nthreads)
@@ -299,7 +300,7 @@ int oracle_fill_cells(int64_t n, const float *pos, const int32_t *type, int32_t 
 }
 
 /* Squared minimum-image distance of one pair, exposed for band-pair reports. */
-double oracle_pair_d2(const float *pi, const float *pj, const double *box)
+double oracle_pair_d2(const double *pi, const double *pj, const double *box)
 {
     return pair_d2(pi, pj, box);
 }

@@ -200,3 +200,63 @@ def test_generators_stay_in_half_open_box():
     x = np.array([[-1e-12, 10.0, 9.9999999999]])
     w = W.wrap_f32(x, np.full(3, 10.0, np.float32))
     assert np.all(w >= 0) and np.all(w < 10.0)
+
+
+# ---------------------------------------------------------------- fp64 particle data
+
+def _lists64(pos, box, rc, skin, method="brute"):
+    rp, cols = oracle.neighbor_lists(np.asarray(pos, np.float64), np.asarray(box, np.float64),
+                                     np.array([[rc]], np.float32), skin, method=method)
+    return rows_as_sets(rp, cols)
+
+
+@pytest.mark.parametrize("method", ["brute", "cells"])
+def test_fp64_pairs_closer_than_fp32_resolves(method):
+    # r_list = 1.5 exactly (rc 1.5 and skin 0 are exact in fp32); pairs 1.5 -/+ 1e-12
+    # apart along x, at positions fp32 cannot tell apart from the tie
+    r = 1.5
+    box = [9.0, 9.0, 9.0]
+    x0 = 3.1
+    inside = np.array([[x0, 4.0, 4.0], [x0 + r - 1e-12, 4.0, 4.0]])
+    outside = np.array([[x0, 4.0, 4.0], [x0 + r + 1e-12, 4.0, 4.0]])
+    assert _lists64(inside, box, r, 0.0, method) == [{1}, {0}]
+    assert _lists64(outside, box, r, 0.0, method) == [set(), set()]
+    # the fp32 images of the two cases are the same pair of points
+    assert np.array_equal(inside.astype(np.float32), outside.astype(np.float32))
+
+
+def test_fp64_minimum_image_across_face():
+    box = [10.0, 10.0, 10.0]
+    p = np.array([[1e-13, 5.0, 5.0], [10.0 - 0.75, 5.0, 5.0]])  # 0.75 + 1e-13 apart across x
+    assert _lists64(p, box, 0.75, 0.0) == [set(), set()]
+    p[0, 0] = 0.0
+    assert _lists64(p, box, 0.75, 0.0) == [{1}, {0}]
+
+
+def test_fp64_brute_equals_cells_and_is_symmetric():
+    rng = np.random.default_rng(64)
+    box = np.array([13.0, 17.0, 19.0])
+    pos = rng.uniform(0.0, 1.0, size=(3000, 3)) * box
+    rb, cb = oracle.neighbor_lists(pos, box, np.array([[2.2]], np.float32), 0.3, method="brute")
+    rc_, cc = oracle.neighbor_lists(pos, box, np.array([[2.2]], np.float32), 0.3, method="cells")
+    assert np.array_equal(rb, rc_) and np.array_equal(cb, cc)
+    rows = rows_as_sets(rb, cb)
+    for i, s in enumerate(rows):
+        assert i not in s and all(i in rows[j] for j in s)
+
+
+def test_fp64_lists_differ_from_their_fp32_rounding_only_near_the_cutoff():
+    # the fp64 definition is used as given: rounding the data to fp32 moves only
+    # pairs whose fp64 distance is within a few fp32 ulps of r_list
+    c = W.lj_fluid(4000)
+    rng = np.random.default_rng(5)
+    pos64 = np.mod(c.pos.astype(np.float64) + rng.uniform(-4e-7, 4e-7, size=c.pos.shape), c.box.astype(np.float64))
+    box64 = c.box.astype(np.float64)
+    r64, c64 = oracle.neighbor_lists(pos64, box64, c.rcut, c.skin)
+    r32, c32 = oracle.neighbor_lists(pos64.astype(np.float32), c.box, c.rcut, c.skin)
+    a, b = rows_as_sets(r64, c64), rows_as_sets(r32, c32)
+    R = float(np.float32(c.rcut[0, 0])) + float(np.float32(c.skin))
+    for i in range(c.n):
+        for j in a[i] ^ b[i]:
+            d = math.sqrt(oracle.pair_d2(pos64[i], pos64[j], box64))
+            assert abs(d - R) < 1e-5, (i, j, d)
