@@ -114,6 +114,28 @@ QBVH_API int qbvh_build(qbvh_t **tree, const float *d_pos, const int32_t *d_type
                qbvh_stream_t stream);
 
 /*
+ * qbvh_build_f64 -- the same build for fp64 particle data (the paper's fp64
+ * case: Section 2.2, where fp32 bounds that contain the fp64 data keep the
+ * tree small, and Figs. 4-7).
+ *
+ *   d_pos   device double [n][3], every coordinate in [0, box[d]).
+ *   box     host double [3]: box edges, all > 0 and finite.
+ *   (tree, d_type, n, ntypes, opts as qbvh_build.)
+ *
+ * The tree is built and walked on the positions rounded to fp32; the fp64
+ * positions are kept in sorted order, and every pair whose fp32 distance is
+ * within the rounding band of the cutoff is decided with them.  nlist_build
+ * on such a tree returns the exact list of the fp64 data (the definition at
+ * the top with dx computed from the fp64 coordinates and the fp64 box).
+ * Paper-mode lists (nlist_build_ex with QBVH_LIST_PAPER) return QBVH_ENOTSUP
+ * for it.  d_pos must stay valid until the build's work on the stream is done.
+ * Errors as qbvh_build; validate = 1 checks the fp64 coordinates.
+ */
+QBVH_API int qbvh_build_f64(qbvh_t **tree, const double *d_pos, const int32_t *d_type, int32_t n,
+                   int32_t ntypes, const double box[3], const qbvh_opts_t *opts,
+                   qbvh_stream_t stream);
+
+/*
  * nlist_build -- traverse the tree once per particle (Algorithm 1, eq. (2),
  * Section 2.3) and write the exact neighbor list defined at the top.
  *

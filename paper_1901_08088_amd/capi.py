@@ -22,7 +22,7 @@ OK, EINVAL, EGEOM, ENOMEM, EHIP, EAGAIN, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 EXPORT = dict(keys=1, perm=2, sorted=3, left=4, right=5, range_f=6, range_l=7, parent=8,
               leaf_parent=9, box_lo=10, box_hi=11, records=12, ropes=13)
 
-C_API = ("qbvh_build", "nlist_build", "nlist_build_ex", "nlist_build_many", "nlist_batch_stats", "nlist_batch_release",
+C_API = ("qbvh_build", "qbvh_build_f64", "nlist_build", "nlist_build_ex", "nlist_build_many", "nlist_batch_stats", "nlist_batch_release",
          "qbvh_server_create", "qbvh_server_submit", "qbvh_server_poll", "qbvh_server_wait",
          "qbvh_server_result", "qbvh_server_stats", "qbvh_server_destroy",
          "qbvh_free", "qbvh_strerror", "qbvh_last_hip_error", "qbvh_workspace_bytes", "qbvh_info",
@@ -106,6 +106,9 @@ def lib():
             L.qbvh_build.argtypes = [ctypes.POINTER(P), P, P, I32, I32, ctypes.POINTER(ctypes.c_float),
                                      ctypes.POINTER(QbvhOpts), P]
             L.qbvh_build.restype = ctypes.c_int
+            L.qbvh_build_f64.argtypes = [ctypes.POINTER(P), P, P, I32, I32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(QbvhOpts), P]
+            L.qbvh_build_f64.restype = ctypes.c_int
             L.nlist_build.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_float, I32, P, P, P, P]
             L.nlist_build.restype = ctypes.c_int
             L.nlist_build_ex.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_float, I32, I32, P, P, P, P]
@@ -203,19 +206,27 @@ class Tree:
 
 def qbvh_build(pos, types=None, box=None, ntypes: int = 1, opts=None, tree: Tree | None = None,
                stream=None) -> Tree:
-    """Build (or rebuild in place) the quantized BVH of ``pos`` (float32 [n, 3] on the GPU)."""
+    """Build (or rebuild in place) the quantized BVH of ``pos`` ([n, 3] on the GPU):
+    float32 data through qbvh_build, float64 data through qbvh_build_f64 (the
+    box is then taken in fp64)."""
     import torch
     t = tree if tree is not None else Tree()
     n = int(pos.shape[0]) if pos is not None else 0
     if pos is not None and (pos.dim() != 2 or pos.shape[1] != 3):
         raise ValueError("pos must have shape [n, 3]")
-    pp = _dev_ptr(pos, torch.float32, "pos")
+    f64 = pos is not None and pos.dtype == torch.float64
+    pp = _dev_ptr(pos, torch.float64 if f64 else torch.float32, "pos")
     tp = _dev_ptr(types, torch.int32, "types", allow_none=True)
-    b = (ctypes.c_float * 3)(*[float(x) for x in np.asarray(box, dtype=np.float32).reshape(3)])
     o = _opts(opts)
-    rc = lib().qbvh_build(ctypes.byref(t.ptr), pp, tp, n, int(ntypes), b,
-                          ctypes.byref(o) if o is not None else None, _stream(stream))
-    _check(rc, "qbvh_build")
+    if f64:
+        b = (ctypes.c_double * 3)(*[float(x) for x in np.asarray(box, dtype=np.float64).reshape(3)])
+        rc = lib().qbvh_build_f64(ctypes.byref(t.ptr), pp, tp, n, int(ntypes), b,
+                                  ctypes.byref(o) if o is not None else None, _stream(stream))
+    else:
+        b = (ctypes.c_float * 3)(*[float(x) for x in np.asarray(box, dtype=np.float32).reshape(3)])
+        rc = lib().qbvh_build(ctypes.byref(t.ptr), pp, tp, n, int(ntypes), b,
+                              ctypes.byref(o) if o is not None else None, _stream(stream))
+    _check(rc, "qbvh_build_f64" if f64 else "qbvh_build")
     t.ntypes = int(ntypes)
     return t
 

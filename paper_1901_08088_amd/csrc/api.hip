@@ -20,6 +20,16 @@ struct qbvh {
     float box[3] = {0.f, 0.f, 0.f};
     qbvh_opts_t opts{};
     hipStream_t stream = nullptr;
+    // fp64 particle data (qbvh_build_f64): the box in fp64 and, in one extra
+    // allocation for cap64 particles, the data rounded to fp32 (the build's
+    // input), the sorted fp64 positions (the exact decisions) and an error word
+    int32_t f64 = 0;
+    double box64[3] = {0.0, 0.0, 0.0};
+    void *mem64 = nullptr;
+    int32_t cap64 = 0;
+    float *pos32 = nullptr;
+    double *sorted64 = nullptr;
+    int32_t *err64 = nullptr;
 };
 
 namespace {
@@ -58,6 +68,12 @@ bool box_ok(const float box[3]) {
 // (rc + skin)^2 in fp64 from the fp32 inputs; -1 marks a pair never listed.
 int list_radii(const float *rcut, float skin, int32_t ntypes, const float box[3],
                double rlist2[QBVH_MAX_TYPES * QBVH_MAX_TYPES]) {
+    const double b[3] = {(double)box[0], (double)box[1], (double)box[2]};
+    return list_radii(rcut, skin, ntypes, b, rlist2);
+}
+
+int list_radii(const float *rcut, float skin, int32_t ntypes, const double box[3],
+               double rlist2[QBVH_MAX_TYPES * QBVH_MAX_TYPES]) {
     if (!rcut || !(isfinite(skin) && skin >= 0.0f)) return QBVH_EINVAL;
     double rmax = 0.0;
     for (int a = 0; a < QBVH_MAX_TYPES * QBVH_MAX_TYPES; ++a) rlist2[a] = -1.0;
@@ -73,15 +89,20 @@ int list_radii(const float *rcut, float skin, int32_t ntypes, const float box[3]
             }
         }
     }
-    const double lmin = fmin((double)box[0], fmin((double)box[1], (double)box[2]));
+    const double lmin = fmin(box[0], fmin(box[1], box[2]));
     if (!(2.0 * rmax * (1.0 + 1e-9) < lmin)) return QBVH_EGEOM;
     return QBVH_OK;
 }
 
 void fill_trav_box(TravArgs &a, const float box[3]) {
+    const double b[3] = {(double)box[0], (double)box[1], (double)box[2]};
+    fill_trav_box(a, b);
+}
+
+void fill_trav_box(TravArgs &a, const double box[3]) {
     for (int d = 0; d < 3; ++d) {
-        a.L[d] = (double)box[d];
-        a.Lf[d] = box[d];
+        a.L[d] = box[d];
+        a.Lf[d] = (float)box[d];
     }
     a.lmax = fmax(a.L[0], fmax(a.L[1], a.L[2]));
 }
@@ -120,20 +141,18 @@ size_t qbvh_workspace_bytes(int32_t n, int32_t ntypes, const qbvh_opts_t *opts) 
 void qbvh_free(qbvh_t *tree) {
     if (!tree) return;
     if (tree->ws.base) (void)hipFree(tree->ws.base);
+    if (tree->mem64) (void)hipFree(tree->mem64);
     delete tree;
 }
 
-int qbvh_build(qbvh_t **tree, const float *d_pos, const int32_t *d_type, int32_t n, int32_t ntypes,
-               const float box[3], const qbvh_opts_t *opts, qbvh_stream_t stream) {
-    if (!tree || n < 0 || n > kMaxParticles || ntypes < 1 || ntypes > QBVH_MAX_TYPES || !box_ok(box))
-        return QBVH_EINVAL;
-    if (n > 0 && !d_pos) return QBVH_EINVAL;
-    if (n > 0 && ntypes > 1 && !d_type) return QBVH_EINVAL;
-    qbvh_opts_t o;
-    int rc = resolve_opts(opts, &o);
-    if (rc != QBVH_OK) return rc;
-    hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
 
+namespace {
+
+// The tree of a build call: `*tree` itself, or a new one; its workspace is
+// kept when it holds n particles, otherwise reallocated after both streams
+// drain.  Returns QBVH_OK and the tree in *out (stored in *tree on success).
+int prepare_tree(qbvh_t **tree, int32_t n, hipStream_t s, qbvh_t **out) {
     qbvh_t *t = *tree;
     const bool fresh = (t == nullptr);
     if (fresh) {
@@ -161,24 +180,105 @@ int qbvh_build(qbvh_t **tree, const float *d_pos, const int32_t *d_type, int32_t
         }
         qbi::workspace_carve(t->ws, base, cap);
     }
+    *out = t;
+    *tree = t;
+    return QBVH_OK;
+}
+
+// Waits for the build and reads the device-side validation word.
+int check_valid(const int32_t *d_err, hipStream_t s) {
+    int32_t err = 0;
+    hipError_t e = hipMemcpyAsync(&err, d_err, sizeof(err), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e);
+    return err ? QBVH_EINVAL : QBVH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qbvh_build(qbvh_t **tree, const float *d_pos, const int32_t *d_type, int32_t n, int32_t ntypes,
+               const float box[3], const qbvh_opts_t *opts, qbvh_stream_t stream) {
+    if (!tree || n < 0 || n > kMaxParticles || ntypes < 1 || ntypes > QBVH_MAX_TYPES || !box_ok(box))
+        return QBVH_EINVAL;
+    if (n > 0 && !d_pos) return QBVH_EINVAL;
+    if (n > 0 && ntypes > 1 && !d_type) return QBVH_EINVAL;
+    qbvh_opts_t o;
+    int rc = resolve_opts(opts, &o);
+    if (rc != QBVH_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    qbvh_t *t = nullptr;
+    rc = prepare_tree(tree, n, s, &t);
+    if (rc != QBVH_OK) return rc;
     t->n = n;
     t->ntypes = ntypes;
     memcpy(t->box, box, sizeof(t->box));
+    t->f64 = 0;
     t->opts = o;
     t->stream = s;
-    *tree = t;
 
     hipError_t e = qbi::launch_build(t->ws, d_pos, ntypes > 1 ? d_type : nullptr, n, ntypes, box, o.leaf_size,
                                       o.qbits, o.validate, s);
     if (e != hipSuccess) return hip_fail(e);
-    if (o.validate) {
-        int32_t err = 0;
-        e = hipMemcpyAsync(&err, t->ws.err, sizeof(err), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return o.validate ? check_valid(t->ws.err, s) : QBVH_OK;
+}
+
+int qbvh_build_f64(qbvh_t **tree, const double *d_pos, const int32_t *d_type, int32_t n, int32_t ntypes,
+                   const double box[3], const qbvh_opts_t *opts, qbvh_stream_t stream) {
+    if (!tree || n < 0 || n > kMaxParticles || ntypes < 1 || ntypes > QBVH_MAX_TYPES || !box)
+        return QBVH_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (!(isfinite(box[d]) && box[d] > 0.0 && box[d] < 3.0e38)) return QBVH_EINVAL;
+    if (n > 0 && !d_pos) return QBVH_EINVAL;
+    if (n > 0 && ntypes > 1 && !d_type) return QBVH_EINVAL;
+    qbvh_opts_t o;
+    int rc = resolve_opts(opts, &o);
+    if (rc != QBVH_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    qbvh_t *t = nullptr;
+    rc = prepare_tree(tree, n, s, &t);
+    if (rc != QBVH_OK) return rc;
+    if (t->mem64 == nullptr || t->cap64 < n) {
+        if (t->mem64) {
+            hipError_t e = hipStreamSynchronize(t->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e);
+            (void)hipFree(t->mem64);
+            t->mem64 = nullptr;
+            t->cap64 = 0;
+        }
+        const int32_t cap = n > 0 ? n : 1;
+        const size_t b32 = ((size_t)cap * 12 + 255) & ~(size_t)255;
+        void *m = nullptr;
+        hipError_t e = hipMalloc(&m, b32 + (size_t)cap * 32 + 256);
         if (e != hipSuccess) return hip_fail(e);
-        if (err) return QBVH_EINVAL;
+        t->mem64 = m;
+        t->cap64 = cap;
+        t->pos32 = (float *)m;
+        t->sorted64 = (double *)((char *)m + b32);
+        t->err64 = (int32_t *)((char *)m + b32 + (size_t)cap * 32);
     }
-    return QBVH_OK;
+    t->n = n;
+    t->ntypes = ntypes;
+    for (int d = 0; d < 3; ++d) {
+        t->box64[d] = box[d];
+        t->box[d] = (float)box[d];
+    }
+    t->f64 = 1;
+    t->opts = o;
+    t->stream = s;
+
+    // the build runs on the data rounded to fp32 (a point may round onto the
+    // box edge, which the Morton bins clamp); validation is done here in fp64
+    hipError_t e = qbi::launch_to_f32(d_pos, ntypes > 1 ? d_type : nullptr, n, ntypes, box, o.validate, t->pos32,
+                                      t->err64, s);
+    if (e == hipSuccess)
+        e = qbi::launch_build(t->ws, t->pos32, ntypes > 1 ? d_type : nullptr, n, ntypes, t->box, o.leaf_size,
+                              o.qbits, 0, s);
+    if (e == hipSuccess) e = qbi::launch_gather64(t->ws, n, d_pos, t->sorted64, s);
+    if (e != hipSuccess) return hip_fail(e);
+    return o.validate ? check_valid(t->err64, s) : QBVH_OK;
 }
 
 int nlist_build_ex(const qbvh_t *tree, const float *rcut, float skin, int32_t max_nbr, int32_t mode,
@@ -186,8 +286,10 @@ int nlist_build_ex(const qbvh_t *tree, const float *rcut, float skin, int32_t ma
     if (!tree || max_nbr < 0 || !d_overflow) return QBVH_EINVAL;
     if (mode != QBVH_LIST_EXACT && mode != QBVH_LIST_PAPER) return QBVH_EINVAL;
     if (tree->n > 0 && (!d_count || (max_nbr > 0 && !d_nbr))) return QBVH_EINVAL;
+    if (tree->f64 && mode == QBVH_LIST_PAPER) return QBVH_ENOTSUP;
     qbi::TravArgs a{};
-    int rc = list_radii(rcut, skin, tree->ntypes, tree->box, a.rlist2);
+    int rc = tree->f64 ? list_radii(rcut, skin, tree->ntypes, tree->box64, a.rlist2)
+                       : list_radii(rcut, skin, tree->ntypes, tree->box, a.rlist2);
     if (rc != QBVH_OK) return rc;
     a.records = tree->ws.records;
     a.ropes = tree->ws.ropes;
@@ -196,7 +298,12 @@ int nlist_build_ex(const qbvh_t *tree, const float *rcut, float skin, int32_t ma
     a.nbr = d_nbr;
     a.count = d_count;
     a.overflow = d_overflow;
-    qbi::fill_trav_box(a, tree->box);
+    if (tree->f64) {
+        qbi::fill_trav_box(a, tree->box64);
+        a.sorted64 = tree->sorted64;
+    } else {
+        qbi::fill_trav_box(a, tree->box);
+    }
     a.n = tree->n;
     a.ntypes = tree->ntypes;
     a.max_nbr = max_nbr;

@@ -84,6 +84,47 @@ __global__ __launch_bounds__(kBuildThreads) void k_gather(const float *__restric
     sorted[k] = p;
 }
 
+// fp64 particle data, before the build: each coordinate rounded to nearest
+// fp32 (the tree is built and walked on these; the exact decisions use the
+// fp64 values), with the fp64 checks 0 <= x < L and 0 <= type < ntypes when
+// `validate` is set (*err, cleared by k_clear_err before, is set on failure).
+__global__ void k_clear_err(int32_t *err) {
+    if (threadIdx.x == 0) *err = 0;
+}
+
+__global__ __launch_bounds__(kBuildThreads) void k_to_f32(const double *__restrict__ pos64,
+                                                          const int32_t *__restrict__ type, int32_t n,
+                                                          int32_t ntypes, double Lx, double Ly, double Lz,
+                                                          int32_t validate, float *__restrict__ pos32,
+                                                          int32_t *err) {
+    const int32_t i = blockIdx.x * kBuildThreads + threadIdx.x;
+    if (i >= n) return;
+    const double x = pos64[3 * (int64_t)i + 0], y = pos64[3 * (int64_t)i + 1], z = pos64[3 * (int64_t)i + 2];
+    if (validate) {
+        const int32_t t = type ? type[i] : 0;
+        const bool ok = (x >= 0.0 && x < Lx) && (y >= 0.0 && y < Ly) && (z >= 0.0 && z < Lz) && t >= 0 && t < ntypes;
+        if (!ok) atomicOr(err, 1);
+    }
+    pos32[3 * (int64_t)i + 0] = (float)x;
+    pos32[3 * (int64_t)i + 1] = (float)y;
+    pos32[3 * (int64_t)i + 2] = (float)z;
+}
+
+// fp64 particle data, after the build: the fp64 position of every sorted
+// particle (its input index is the inverted w word of the fp32 copy).
+__global__ __launch_bounds__(kBuildThreads) void k_gather64(const float4 *__restrict__ sorted, int32_t n,
+                                                            const double *__restrict__ pos64,
+                                                            double *__restrict__ sorted64) {
+    const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
+    if (k >= n) return;
+    const int64_t i = ~__float_as_int(sorted[k].w);
+    double *o = sorted64 + 4 * (int64_t)k;
+    o[0] = pos64[3 * i + 0];
+    o[1] = pos64[3 * i + 1];
+    o[2] = pos64[3 * i + 2];
+    o[3] = 0.0;
+}
+
 // Karras's parallel construction: internal node i of a segment covers a
 // range with i at one end; its direction, far end and split are found by
 // exponential then binary search on the common-prefix length.
@@ -378,6 +419,21 @@ inline dim3 grid_for(int64_t items) { return dim3((unsigned)((items + kBuildThre
 }  // namespace
 
 int32_t fit_chunks0(int32_t cap) { return (cap + kFitChunk - 1) / kFitChunk; }
+
+hipError_t launch_to_f32(const double *pos64, const int32_t *type, int32_t n, int32_t ntypes, const double box[3],
+                         int32_t validate, float *pos32, int32_t *err, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(64), 0, s, err);
+    if (n > 0)
+        hipLaunchKernelGGL(k_to_f32, grid_for(n), dim3(kBuildThreads), 0, s, pos64, type, n, ntypes, box[0], box[1],
+                           box[2], validate, pos32, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather64(const Workspace &w, int32_t n, const double *pos64, double *sorted64, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_gather64, grid_for(n), dim3(kBuildThreads), 0, s, w.sorted, n, pos64, sorted64);
+    return hipGetLastError();
+}
 
 hipError_t launch_fit(const Workspace &w, int32_t n, hipStream_t s) {
     int32_t nchunks = fit_chunks0(n);

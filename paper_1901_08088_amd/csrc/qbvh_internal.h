@@ -80,6 +80,7 @@ struct TravArgs {
     const int32_t *ropes;
     const float4 *sorted;
     const TreeMeta *meta;
+    const double *sorted64;  // fp64 data: sorted positions [n][4] (x, y, z, unused); nullptr for fp32 data
     int32_t *nbr;
     int32_t *count;
     int32_t *overflow;
@@ -157,7 +158,10 @@ int hip_fail(hipError_t e);  // records the error for qbvh_last_hip_error, maps 
 bool box_ok(const float box[3]);
 int list_radii(const float *rcut, float skin, int32_t ntypes, const float box[3],
                double rlist2[QBVH_MAX_TYPES * QBVH_MAX_TYPES]);
+int list_radii(const float *rcut, float skin, int32_t ntypes, const double box[3],
+               double rlist2[QBVH_MAX_TYPES * QBVH_MAX_TYPES]);
 void fill_trav_box(TravArgs &a, const float box[3]);
+void fill_trav_box(TravArgs &a, const double box[3]);
 
 // Launchers (all asynchronous on `s`; return the launch status).
 hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d_type, int32_t n,
@@ -165,6 +169,12 @@ hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d
                         int32_t validate, hipStream_t s);
 hipError_t launch_traverse(const TravArgs &a, int32_t block, bool vec4, bool paper, const uint4 *qpoint,
                            hipStream_t s);
+// fp64 particle data: the positions rounded to fp32 for the build (with the
+// fp64 range and type checks when validate is set), and after the build the
+// fp64 positions in sorted order.
+hipError_t launch_to_f32(const double *pos64, const int32_t *type, int32_t n, int32_t ntypes, const double box[3],
+                         int32_t validate, float *pos32, int32_t *err, hipStream_t s);
+hipError_t launch_gather64(const Workspace &w, int32_t n, const double *pos64, double *sorted64, hipStream_t s);
 hipError_t launch_qpoint(const Workspace &w, int32_t n, int32_t ntypes, int32_t qbits, hipStream_t s);
 hipError_t launch_traverse_batch(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t s);

@@ -264,11 +264,11 @@ __device__ __forceinline__ void run_paper(const uint4 *__restrict__ qrun, uint32
 // of up to 16 particles is taken in halves of at most 8: each half adds at
 // most 8 entries to a ring holding fewer than kFlush, and the ring is
 // flushed after every half.
-template <bool kVec4, int kBlock, bool kPaper, class LArr>
+template <bool kVec4, int kBlock, bool kPaper, bool kF64, class LArr>
 __device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, Lane &q, int img, const LArr &L,
                                          const float4 *__restrict__ sorted, const uint4 *__restrict__ qpoint,
-                                         uint32_t nend, int32_t (*s_out)[kBlock], int32_t *s_src, int32_t *nbr,
-                                         int32_t max_nbr) {
+                                         const double *__restrict__ sorted64, uint32_t nend,
+                                         int32_t (*s_out)[kBlock], int32_t *s_src, int32_t *nbr, int32_t max_nbr) {
     const int32_t v = ~ref;
     const uint32_t first = (uint32_t)uniform(v >> kRunCountBits);
     const uint32_t count = (uint32_t)uniform((v & kRunCountMask) + 1);
@@ -305,14 +305,19 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, L
                 const double sx = (double)(img % 3 - 1) * L[0];
                 const double sy = (double)((img / 3) % 3 - 1) * L[1];
                 const double sz = (double)(img / 9 - 1) * L[2];
+                // fp64 data: the query's and the candidates' own fp64 positions
+                const double *q64 = kF64 ? sorted64 + 4 * (int64_t)(hit ? q.k : (int32_t)first) : nullptr;
+                const double qx = kF64 ? q64[0] : (double)q.x, qy = kF64 ? q64[1] : (double)q.y,
+                             qz = kF64 ? q64[2] : (double)q.z;
                 for (uint32_t j = 0; j < c8; ++j) {
                     const float4 p = particle(sbase, roff, j);
                     const float ax = p.x - q.qsx, ay = p.y - q.qsy, az = p.z - q.qsz;
                     const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
                     if (hit && !(d2 <= thr) && d2 <= q.r2out && j != rel) {
-                        const double dx = ((double)p.x - (double)q.x) - sx;
-                        const double dy = ((double)p.y - (double)q.y) - sy;
-                        const double dz = ((double)p.z - (double)q.z) - sz;
+                        const double *p64 = kF64 ? sorted64 + 4 * (int64_t)(first + h0 + j) : nullptr;
+                        const double dx = ((kF64 ? p64[0] : (double)p.x) - qx) - sx;
+                        const double dy = ((kF64 ? p64[1] : (double)p.y) - qy) - sy;
+                        const double dz = ((kF64 ? p64[2] : (double)p.z) - qz) - sz;
                         if ((dx * dx + dy * dy) + dz * dz <= q.r2) {
                             s_out[q.cnt & (kRing - 1)][threadIdx.x] = ~__float_as_int(p.w);
                             ++q.cnt;
@@ -328,11 +333,12 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, L
 
 // The read-only arrays come as separate __restrict__ parameters: that lets the
 // compiler fetch wave-uniform records and particles with scalar loads.
-template <bool kVec4, int kBlock, bool kPaper, class Args>
+template <bool kVec4, int kBlock, bool kPaper, bool kF64, class Args>
 __device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 *__restrict__ records,
                                                const int32_t *__restrict__ ropes,
                                                const float4 *__restrict__ sorted,
                                                const uint4 *__restrict__ qpoint,
+                                               const double *__restrict__ sorted64,
                                                const TreeMeta *__restrict__ meta, int32_t (*s_out)[kBlock],
                                                int32_t (*s_src)[64]);
 
@@ -380,14 +386,15 @@ __device__ __forceinline__ int32_t query_position(Args &a, const TreeMeta *__res
     return a.n;
 }
 
-template <bool kVec4, int kBlock, bool kPaper>
+template <bool kVec4, int kBlock, bool kPaper, bool kF64>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_traverse(
     TravArgs a, const uint4 *__restrict__ records, const int32_t *__restrict__ ropes,
     const float4 *__restrict__ sorted, const uint4 *__restrict__ qpoint, const TreeMeta *__restrict__ meta) {
     __shared__ int32_t s_out[kRing][kBlock];
     __shared__ int32_t s_src[kBlock / 64][64];
     const int32_t li = query_position<kBlock>(a, meta, xcd_logical_block(), (int32_t)gridDim.x);
-    traverse_block<kVec4, kBlock, kPaper, const TravArgs>(a, li, records, ropes, sorted, qpoint, meta, s_out, s_src);
+    traverse_block<kVec4, kBlock, kPaper, kF64, const TravArgs>(a, li, records, ropes, sorted, qpoint, a.sorted64, meta,
+                                                                s_out, s_src);
 }
 
 // Batched form: the workgroups of all systems form one grid; each workgroup
@@ -410,16 +417,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     ConstArgs *args = reinterpret_cast<ConstArgs *>(reinterpret_cast<uintptr_t>(table + sys));
     const TreeMeta *meta = meta_all + sys * QBVH_MAX_TYPES;
     const int32_t li = query_position<kBlock>(*args, meta, logical - tblk_first[sys], tblk_first[sys + 1] - tblk_first[sys]);
-    traverse_block<kVec4, kBlock, false, ConstArgs>(*args, li, records, ropes, sorted, nullptr, meta, s_out, s_src);
+    traverse_block<kVec4, kBlock, false, false, ConstArgs>(*args, li, records, ropes, sorted, nullptr, nullptr, meta,
+                                                           s_out, s_src);
 }
 
 // One workgroup of queries; this lane's query is position `li` of the system
 // `a` (li >= a.n: an idle lane).
-template <bool kVec4, int kBlock, bool kPaper, class Args>
+template <bool kVec4, int kBlock, bool kPaper, bool kF64, class Args>
 __device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 *__restrict__ records,
                                                const int32_t *__restrict__ ropes,
                                                const float4 *__restrict__ sorted,
                                                const uint4 *__restrict__ qpoint,
+                                               const double *__restrict__ sorted64,
                                                const TreeMeta *__restrict__ meta, int32_t (*s_out)[kBlock],
                                                int32_t (*s_src_all)[64]) {
     int32_t *s_src = s_src_all[threadIdx.x >> 6];
@@ -484,7 +493,9 @@ __device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 
         const double rg = R * m.inv_h;
         const double rgp = rg * (1.0 + 0x1p-20) + 2.0;
         const float r2g = lane_on ? (float)(rgp * rgp * (1.0 + 0x1p-20)) : -1.0f;
-        const double eta = 1.7320508075688772 * 0x1p-22 * (2.0 * a.lmax + 2.0 * R);
+        // fp64 data adds the rounding of both points to fp32 (2^-24 L each per
+        // axis); the band is doubled for it
+        const double eta = (kF64 ? 2.0 : 1.0) * 1.7320508075688772 * 0x1p-22 * (2.0 * a.lmax + 2.0 * R);
         const double rin = fmax(R - eta, 0.0) * (1.0 - 0x1p-20);
         const double rout = (R + eta) * (1.0 + 0x1p-20);
         q.r2in = (float)(rin * rin * (1.0 - 0x1p-20));
@@ -518,7 +529,8 @@ __device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 
                 q.pz = (float)((((double)q.z + sz) - (double)m.lo[2]) * m.inv_h);
             }
             if (root < 0) {  // a tree of at most leaf_size particles is one run
-                take_run<kVec4, kBlock, kPaper>(root, on, __ballot(on), q, img, a.L, sorted, qpoint, nend, s_out,
+                take_run<kVec4, kBlock, kPaper, kF64>(root, on, __ballot(on), q, img, a.L, sorted, qpoint, sorted64,
+                                                      nend, s_out,
                                                 s_src, a.nbr, a.max_nbr);
                 continue;
             }
@@ -536,10 +548,12 @@ __device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 
                 const bool anyl = ml != 0, anyr = mr != 0;
                 const int32_t cl = (int32_t)r1.z, cr = (int32_t)r1.w;
                 if (cl < 0 && anyl)
-                    take_run<kVec4, kBlock, kPaper>(cl, hl, ml, q, img, a.L, sorted, qpoint, nend, s_out, s_src,
+                    take_run<kVec4, kBlock, kPaper, kF64>(cl, hl, ml, q, img, a.L, sorted, qpoint, sorted64, nend,
+                                                          s_out, s_src,
                                                     a.nbr, a.max_nbr);
                 if (cr < 0 && anyr)
-                    take_run<kVec4, kBlock, kPaper>(cr, hr, mr, q, img, a.L, sorted, qpoint, nend, s_out, s_src,
+                    take_run<kVec4, kBlock, kPaper, kF64>(cr, hr, mr, q, img, a.L, sorted, qpoint, sorted64, nend,
+                                                          s_out, s_src,
                                                     a.nbr, a.max_nbr);
                 const int32_t next = (anyl && cl >= 0) ? cl : ((anyr && cr >= 0) ? cr : rope);
                 // references always point forward; max() makes progress unconditional
@@ -562,11 +576,11 @@ __global__ void k_clear_flag(int32_t *f) {
     if (threadIdx.x == 0) *f = 0;
 }
 
-template <bool kVec4, int kBlock, bool kPaper>
+template <bool kVec4, int kBlock, bool kPaper, bool kF64>
 void launch_one(const TravArgs &a, const uint4 *qpoint, hipStream_t s) {
     const unsigned grid = (unsigned)trav_blocks(a.n, a.ntypes, kBlock, a.qpw);
-    hipLaunchKernelGGL((k_traverse<kVec4, kBlock, kPaper>), dim3(grid), dim3(kBlock), 0, s, a, a.records, a.ropes,
-                       a.sorted, qpoint, a.meta);
+    hipLaunchKernelGGL((k_traverse<kVec4, kBlock, kPaper, kF64>), dim3(grid), dim3(kBlock), 0, s, a, a.records,
+                       a.ropes, a.sorted, qpoint, a.meta);
 }
 
 template <bool kVec4, int kBlock>
@@ -575,13 +589,13 @@ void launch_one_batch(const BatchLaunch &b, hipStream_t s) {
                        b.tblk_first, b.nsys, b.ws.records, b.ws.ropes, b.ws.sorted, b.meta);
 }
 
-template <bool kVec4, bool kPaper>
+template <bool kVec4, bool kPaper, bool kF64>
 void launch_block(const TravArgs &a, int32_t block, const uint4 *qpoint, hipStream_t s) {
     switch (block) {
-    case 64: launch_one<kVec4, 64, kPaper>(a, qpoint, s); break;
-    case 128: launch_one<kVec4, 128, kPaper>(a, qpoint, s); break;
-    case 192: launch_one<kVec4, 192, kPaper>(a, qpoint, s); break;
-    default: launch_one<kVec4, 256, kPaper>(a, qpoint, s); break;
+    case 64: launch_one<kVec4, 64, kPaper, kF64>(a, qpoint, s); break;
+    case 128: launch_one<kVec4, 128, kPaper, kF64>(a, qpoint, s); break;
+    case 192: launch_one<kVec4, 192, kPaper, kF64>(a, qpoint, s); break;
+    default: launch_one<kVec4, 256, kPaper, kF64>(a, qpoint, s); break;
     }
 }
 
@@ -601,16 +615,21 @@ hipError_t launch_traverse(const TravArgs &a, int32_t block, bool vec4, bool pap
                            hipStream_t s) {
     hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, s, a.overflow);
     if (a.n > 0) {
-        if (paper) {
+        if (paper) {  // fp32 data only
             if (vec4)
-                launch_block<true, true>(a, block, qpoint, s);
+                launch_block<true, true, false>(a, block, qpoint, s);
             else
-                launch_block<false, true>(a, block, qpoint, s);
+                launch_block<false, true, false>(a, block, qpoint, s);
+        } else if (a.sorted64) {
+            if (vec4)
+                launch_block<true, false, true>(a, block, nullptr, s);
+            else
+                launch_block<false, false, true>(a, block, nullptr, s);
         } else {
             if (vec4)
-                launch_block<true, false>(a, block, nullptr, s);
+                launch_block<true, false, false>(a, block, nullptr, s);
             else
-                launch_block<false, false>(a, block, nullptr, s);
+                launch_block<false, false, false>(a, block, nullptr, s);
         }
     }
     return hipGetLastError();

@@ -49,8 +49,8 @@ SEEDS = {
 class Config:
     """One particle configuration plus the cutoff table it is searched with."""
 
-    pos: np.ndarray  # float32 [N, 3]
-    box: np.ndarray  # float32 [3]
+    pos: np.ndarray  # float32 [N, 3] (float64 for fp64 data, see as_f64)
+    box: np.ndarray  # float32 [3] (float64 for fp64 data)
     rcut: np.ndarray  # float32 [ntypes, ntypes]
     skin: float
     types: np.ndarray | None = None  # int32 [N] or None for one type
@@ -278,6 +278,40 @@ def ensemble(n_systems: int = 256, seed=SEEDS["ensemble"], n_min: int = 2000, n_
         out.append(Config(pos=pos, box=box, rcut=np.array([[rc]], dtype=np.float32), skin=skin,
                           name=f"replica{k}_N{n}", meta={"rho": rho, "rc": rc, "index": k}))
     return out
+
+
+def as_f64(cfg: Config, seed, scale: float = 1e-3) -> Config:
+    """fp64 particle data from a configuration: every coordinate moved by a
+    seeded uniform offset of up to ``scale`` sigma in fp64 and wrapped into
+    [0, L) in fp64 (so almost no coordinate is an fp32 value); the box is the
+    same, held as fp64."""
+    rng = np.random.default_rng(seed)
+    box64 = np.asarray(cfg.box, dtype=np.float32).astype(np.float64)
+    x = cfg.pos.astype(np.float64) + rng.uniform(-scale, scale, size=cfg.pos.shape)
+    x = np.mod(x, box64)
+    x = np.where(x >= box64, 0.0, x)  # mod can return L for tiny negative inputs
+    return Config(pos=np.ascontiguousarray(x), box=box64, rcut=cfg.rcut, skin=cfg.skin, types=cfg.types,
+                  name=cfg.name + "_f64", meta=dict(cfg.meta, f64_seed=seed))
+
+
+def near_cutoff_pairs_f64(n_base: int, n_pairs: int, box: float, r_list: float, seed,
+                          rel: tuple[float, float] = (1e-13, 1e-8)) -> Config:
+    """fp64 stress case for the exact decision: ``n_base`` uniform points and,
+    for ``n_pairs`` of them, a partner at distance r_list (1 +- e) in a random
+    direction with e log-uniform in ``rel`` (fp32 cannot resolve these)."""
+    rng = np.random.default_rng(seed)
+    L = float(box)
+    base = rng.uniform(0.0, L, size=(n_base, 3))
+    who = rng.choice(n_base, size=n_pairs, replace=False)
+    u = rng.normal(size=(n_pairs, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    e = np.exp(rng.uniform(np.log(rel[0]), np.log(rel[1]), size=n_pairs)) * rng.choice([-1.0, 1.0], size=n_pairs)
+    partner = base[who] + u * (r_list * (1.0 + e))[:, None]
+    x = np.mod(np.concatenate([base, partner]), L)
+    x = np.where(x >= L, 0.0, x)
+    x = x[rng.permutation(x.shape[0])]
+    return Config(pos=np.ascontiguousarray(x), box=np.full(3, L), rcut=np.array([[np.float32(r_list)]], np.float32),
+                  skin=0.0, name=f"near_cutoff_f64_N{x.shape[0]}", meta={"seed": seed})
 
 
 WCA_RC = 2.0 ** (1.0 / 6.0)
