@@ -92,10 +92,10 @@ def traversal_bytes(n: int, nrecords: int, stored_pairs: int) -> int:
 # factor the same counters read for a plain elementwise copy of known size (the
 # --copy-probe-mib kernel).  Valid only for the kernel sources it was taken on:
 # ``traffic`` is reported as null once their hash differs.
-TRAFFIC = {"sources": "02eae8707c3ef86a", "workload": "lj8m",
+TRAFFIC = {"sources": "d2425906bcf2c140", "workload": "lj8m",
            "opts": {"leaf_size": 16, "qbits": 16, "block_size": 64},
-           "fetch_kib": 1591920.63, "write_kib": 6643493.78, "copy_factor": 1.0,
-           "fetch_factor": 0.500024, "profile": "profiles/k_traverse_lj8m_counters.md",
+           "fetch_kib": 1591345.13, "write_kib": 6643562.95, "copy_factor": 1.0,
+           "fetch_factor": 0.500022, "profile": "profiles/k_traverse_lj8m_counters.md",
            # SQ_ACTIVE_INST_VALU / (SIMDs x kernel cycles / 4): the VALU issues one wave64
            # instruction per 4 cycles per SIMD, so this is the kernel's VALU issue roofline
            "valu_busy": 0.92}
@@ -173,6 +173,45 @@ def paper_mode(cfg, pos, steps: int) -> dict:
     del nbr
     torch.cuda.empty_cache()
     log(f"paper mode: {out}")
+    return out
+
+
+def f64_data(cfg, max_nbr: int, steps: int) -> dict:
+    """The same configuration as fp64 particle data (every coordinate moved by
+    up to 1e-3 sigma in fp64, so it is not an fp32 value): qbvh_build_f64 +
+    nlist_build timed like the main leg; lists exact for the fp64 data."""
+    import torch
+    import paper_1901_08088_amd as Q
+    c64 = W.as_f64(cfg, seed=19010889)
+    n = c64.n
+    pos = torch.from_numpy(c64.pos).cuda()
+    types = None if c64.types is None else torch.from_numpy(c64.types).cuda()
+    nbr = torch.empty((n, max_nbr), dtype=torch.int32, device="cuda")
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    ovf = torch.empty(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    tree = Q.qbvh_build(pos, types, c64.box, c64.ntypes, BENCH_OPTS)
+    for _ in range(2):
+        Q.qbvh_build(pos, types, c64.box, c64.ntypes, BENCH_OPTS, tree=tree)
+        Q.nlist_build(tree, c64.rcut, c64.skin, max_nbr, nbr, cnt, ovf)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for e in ev:
+        e[0].record(stream)
+        Q.qbvh_build(pos, types, c64.box, c64.ntypes, BENCH_OPTS, tree=tree)
+        e[1].record(stream)
+        Q.nlist_build(tree, c64.rcut, c64.skin, max_nbr, nbr, cnt, ovf)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    out = {"workload": "same configuration as fp64 data (offsets up to 1e-3 sigma, seed 19010889)",
+           "build_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
+           "traverse_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in ev])),
+           "directed_pairs": int(cnt.sum()), "overflow": int(ovf.item())}
+    out["builds_per_s"] = 1e3 / (out["build_ms"] + out["traverse_ms"])
+    Q.qbvh_free(tree)
+    del nbr
+    torch.cuda.empty_cache()
+    log(f"fp64 data: {out}")
     return out
 
 
@@ -399,6 +438,8 @@ def main(argv=None) -> int:
                     help="oracle rows timed for the CPU baseline (0 = skip)")
     ap.add_argument("--paper-steps", type=int, default=10,
                     help="traversals timed for the exact-vs-paper-mode comparison (0 = skip)")
+    ap.add_argument("--f64-steps", type=int, default=10,
+                    help="build + traversal steps timed on the same workload as fp64 data (0 = skip)")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="one-system graph-replayed calls timed on the same workload (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=20,
@@ -478,6 +519,11 @@ def main(argv=None) -> int:
         log("paper-mode lists (10-bit grid)")
         paper = paper_mode(cfg, pos, args.paper_steps)
 
+    f64 = None
+    if args.f64_steps > 0:
+        log("fp64 particle data")
+        f64 = f64_data(cfg, max_nbr, args.f64_steps)
+
     graph = None
     if args.graph_steps > 0:
         log("one-system graph replay")
@@ -529,6 +575,7 @@ def main(argv=None) -> int:
         "cpu_baseline": base,
         "paper_mode": paper,
         "single_graph": graph,
+        "f64_data": f64,
         "batched": batched,
         "served": serve,
     }
