@@ -215,6 +215,37 @@ def f64_data(cfg, max_nbr: int, steps: int) -> dict:
     return out
 
 
+def grid_comparator(cfg, pos, max_nbr: int, steps: int) -> dict:
+    """The same lists by the grid method the paper compares its tree with
+    (nlist_build_grid: cells at least as wide as the list radius, 27 cells per
+    particle, rows written entry by entry), timed over ``steps`` calls."""
+    import torch
+    import paper_1901_08088_amd as Q
+    n = cfg.n
+    nbr = torch.empty((n, max_nbr), dtype=torch.int32, device="cuda")
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    ovf = torch.empty(1, dtype=torch.int32, device="cuda")
+    rc, skin = float(cfg.rcut[0, 0]), cfg.skin
+    g = Q.nlist_build_grid(pos, cfg.box, rc, skin, max_nbr, nbr, cnt, ovf)
+    for _ in range(2):
+        Q.nlist_build_grid(pos, cfg.box, rc, skin, max_nbr, nbr, cnt, ovf, grid=g)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(steps):
+        Q.nlist_build_grid(pos, cfg.box, rc, skin, max_nbr, nbr, cnt, ovf, grid=g)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    out = {"method": "uniform grid, cells >= r_list, 27-cell scan, one lane per particle in cell order",
+           "ms": ev[0].elapsed_time(ev[1]) / steps, "directed_pairs": int(cnt.sum())}
+    g.free()
+    del nbr
+    torch.cuda.empty_cache()
+    log(f"grid comparator: {out}")
+    return out
+
+
 def single_graph(cfg, pos, types, max_nbr: int, steps: int) -> dict:
     """The same system as a one-system nlist_build_many call with the bench's
     options fixed (no autotuning): build + traversal replayed from one captured
@@ -438,6 +469,8 @@ def main(argv=None) -> int:
                     help="oracle rows timed for the CPU baseline (0 = skip)")
     ap.add_argument("--paper-steps", type=int, default=10,
                     help="traversals timed for the exact-vs-paper-mode comparison (0 = skip)")
+    ap.add_argument("--grid-steps", type=int, default=5,
+                    help="calls of the grid comparator timed on the same workload (one type only; 0 = skip)")
     ap.add_argument("--f64-steps", type=int, default=10,
                     help="build + traversal steps timed on the same workload as fp64 data (0 = skip)")
     ap.add_argument("--graph-steps", type=int, default=0,
@@ -519,6 +552,14 @@ def main(argv=None) -> int:
         log("paper-mode lists (10-bit grid)")
         paper = paper_mode(cfg, pos, args.paper_steps)
 
+    grid = None
+    if args.grid_steps > 0 and cfg.types is None:
+        log("grid comparator")
+        grid = grid_comparator(cfg, pos, max_nbr, args.grid_steps)
+        grid["tree_speedup"] = grid["ms"] / ms_per_step
+        if grid["directed_pairs"] != pairs:
+            raise RuntimeError(f"grid pairs {grid['directed_pairs']} != tree pairs {pairs}")
+
     f64 = None
     if args.f64_steps > 0:
         log("fp64 particle data")
@@ -576,6 +617,7 @@ def main(argv=None) -> int:
         "paper_mode": paper,
         "single_graph": graph,
         "f64_data": f64,
+        "grid_comparator": grid,
         "batched": batched,
         "served": serve,
     }

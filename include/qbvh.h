@@ -396,6 +396,32 @@ enum {
 QBVH_API int qbvh_export(const qbvh_t *tree, int32_t what, void *d_dst, size_t dst_bytes,
                 qbvh_stream_t stream);
 
+/*
+ * nlist_build_grid -- the same exact list (one particle type) by the grid
+ * method the paper compares its tree with (Section 1 and Section 4: a uniform
+ * grid of cells at least as wide as the list radius; each particle tests the
+ * particles of the 27 cells around its own).  It exists to measure the tree
+ * against a grid on the same GPU.
+ *
+ *   grid    in/out.  *grid == NULL: a new handle is allocated (release with
+ *           qgrid_free); otherwise its device workspace is reused, and
+ *           reallocated after waiting for its pending work when too small.
+ *   d_pos, n, box   as qbvh_build (n >= 0; coordinates in [0, box[d])).
+ *   rcut, skin      list radius rcut + skin (rcut > 0, skin >= 0).
+ *   max_nbr, d_nbr, d_count, d_overflow   as nlist_build (rows hold original
+ *           indices; their order, unspecified, is the same from run to run).
+ *
+ * Cells per axis: floor(L_d / r_list), at most 1024.  Returns QBVH_EGEOM when
+ * 2 r_list >= min L_d and QBVH_ENOTSUP when an axis would hold fewer than 3
+ * cells.  Asynchronous on the stream; d_pos must stay valid until the work is
+ * done.  Inputs are trusted (no device validation).
+ */
+typedef struct qgrid qgrid_t;
+QBVH_API int nlist_build_grid(qgrid_t **grid, const float *d_pos, int32_t n, const float box[3], float rcut,
+                     float skin, int32_t max_nbr, int32_t *d_nbr, int32_t *d_count,
+                     int32_t *d_overflow, qbvh_stream_t stream);
+QBVH_API void qgrid_free(qgrid_t *grid);
+
 #ifdef __cplusplus
 }
 #endif

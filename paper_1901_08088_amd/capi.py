@@ -26,7 +26,7 @@ C_API = ("qbvh_build", "qbvh_build_f64", "nlist_build", "nlist_build_ex", "nlist
          "qbvh_server_create", "qbvh_server_submit", "qbvh_server_poll", "qbvh_server_wait",
          "qbvh_server_result", "qbvh_server_stats", "qbvh_server_destroy",
          "qbvh_free", "qbvh_strerror", "qbvh_last_hip_error", "qbvh_workspace_bytes", "qbvh_info",
-         "qbvh_export")
+         "qbvh_export", "nlist_build_grid", "qgrid_free")
 
 
 class QbvhError(RuntimeError):
@@ -109,6 +109,11 @@ def lib():
             L.qbvh_build_f64.argtypes = [ctypes.POINTER(P), P, P, I32, I32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(QbvhOpts), P]
             L.qbvh_build_f64.restype = ctypes.c_int
+            L.nlist_build_grid.argtypes = [ctypes.POINTER(P), P, I32, ctypes.POINTER(ctypes.c_float), ctypes.c_float,
+                                           ctypes.c_float, I32, P, P, P, P]
+            L.nlist_build_grid.restype = ctypes.c_int
+            L.qgrid_free.argtypes = [P]
+            L.qgrid_free.restype = None
             L.nlist_build.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_float, I32, P, P, P, P]
             L.nlist_build.restype = ctypes.c_int
             L.nlist_build_ex.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_float, I32, I32, P, P, P, P]
@@ -432,3 +437,36 @@ def qbvh_export(tree: Tree, what, dst, stream=None) -> None:
     nbytes = dst.numel() * dst.element_size()
     _check(lib().qbvh_export(tree.ptr, code, ctypes.c_void_p(dst.data_ptr()), nbytes, _stream(stream)),
            "qbvh_export")
+
+
+class Grid:
+    """Handle of the grid comparator's device workspace (nlist_build_grid)."""
+
+    def __init__(self):
+        self.ptr = ctypes.c_void_p()
+
+    def free(self):
+        if self.ptr and self.ptr.value:
+            lib().qgrid_free(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def nlist_build_grid(pos, box, rcut: float, skin: float, max_nbr: int, nbr, count, overflow,
+                     grid: Grid | None = None, stream=None) -> Grid:
+    """Exact one-type neighbor lists by the grid method (the comparator of the tree)."""
+    import torch
+    g = grid if grid is not None else Grid()
+    n = int(pos.shape[0])
+    b = (ctypes.c_float * 3)(*[float(x) for x in np.asarray(box, dtype=np.float32).reshape(3)])
+    rc = lib().nlist_build_grid(ctypes.byref(g.ptr), _dev_ptr(pos, torch.float32, "pos"), n, b, float(rcut),
+                                float(skin), int(max_nbr), _dev_ptr(nbr, torch.int32, "nbr", allow_none=True),
+                                _dev_ptr(count, torch.int32, "count"), _dev_ptr(overflow, torch.int32, "overflow"),
+                                _stream(stream))
+    _check(rc, "nlist_build_grid")
+    return g
