@@ -104,8 +104,11 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_karras(const int32_t *__res
                                                             int32_t *__restrict__ rl, int32_t *__restrict__ parent,
                                                             int32_t *__restrict__ leaf_parent,
                                                             uint32_t *__restrict__ visit, uint32_t *__restrict__ kept) {
+    __shared__ uint32_t s_keys[3 * kBuildThreads];
     const Item it = item_of(blk_first, nsys);
     const SysBuild &y = sysb[it.sys];
+    // the block's first position: blocks never straddle systems
+    const StagedKeys K = stage_keys(keys, s_keys, y.off + it.local - (int32_t)threadIdx.x, y.off, y.off + y.n);
     if (it.local >= y.n) return;
     const int32_t i = y.off + it.local;
     const Segment g = batch_segment(keys[i], y.off, type_count + it.sys * QBVH_MAX_TYPES);
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_karras(const int32_t *__res
         if (g.e - g.s == 1) leaf_parent[i] = -1;
         return;
     }
-    const KarrasNode r = karras_node(keys, i, g);
+    const KarrasNode r = karras_node(K, i, g);
     left[i] = r.left;
     right[i] = r.right;
     rf[i] = r.f;

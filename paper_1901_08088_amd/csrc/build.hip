@@ -135,6 +135,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_karras(const uint32_t *__rest
                                                           int32_t *__restrict__ rl, int32_t *__restrict__ parent,
                                                           int32_t *__restrict__ leaf_parent,
                                                           uint32_t *__restrict__ visit, uint32_t *__restrict__ kept) {
+    __shared__ uint32_t s_keys[3 * kBuildThreads];
+    const StagedKeys K = stage_keys(keys, s_keys, (int32_t)(blockIdx.x * kBuildThreads), 0, n);
     const int32_t i = blockIdx.x * kBuildThreads + threadIdx.x;
     if (i >= n) return;
     const Segment g = segment_of(keys[i], n, ntypes, type_count);
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_karras(const uint32_t *__rest
         if (g.e - g.s == 1) leaf_parent[i] = -1;
         return;
     }
-    const KarrasNode r = karras_node(keys, i, g);
+    const KarrasNode r = karras_node(K, i, g);
     const int32_t gamma = r.gamma, f = r.f, la = r.l, cl = r.left, cr = r.right;
     left[i] = cl;
     right[i] = cr;
