@@ -248,6 +248,99 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
 }
 
+// A whole sort of at most one tile in one workgroup: the four passes of the
+// tile scatter above, each leaving the tile in LDS for the next (a small
+// system's sort in one launch instead of twelve).
+__global__ __launch_bounds__(kSortThreads) void k_radix_sort_tile(uint32_t *__restrict__ keys,
+                                                                  uint32_t *__restrict__ vals, int32_t n) {
+    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ uint32_t s_vals[kSortTile];
+    __shared__ uint32_t s_wcnt[kSortWaves][kRadix];
+    __shared__ uint32_t s_dstart[kRadix];
+    __shared__ uint32_t s_scan[kSortWaves];
+
+    const int tid = threadIdx.x;
+    const int lane = __lane_id();
+    const int wave = tid >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t k[kSortItems], v[kSortItems], r[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int32_t j = wave * 64 * kSortItems + i * 64 + lane;
+        k[i] = j < n ? keys[j] : 0u;
+        v[i] = j < n ? vals[j] : 0u;
+    }
+    for (int pass = 0; pass < 32 / kRadixBits; ++pass) {
+        const int shift = pass * kRadixBits;
+        for (int i = tid; i < kSortWaves * kRadix; i += kSortThreads) (&s_wcnt[0][0])[i] = 0;
+        __syncthreads();
+        // stable rank within the wave's chunk: items in order i, then lane
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const bool valid = wave * 64 * kSortItems + i * 64 + lane < n;
+            const uint32_t d = (k[i] >> shift) & (kRadix - 1);
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < kRadixBits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            if (valid) {
+                const uint32_t before = s_wcnt[wave][d];
+                const uint32_t rk = (uint32_t)__popcll(peers & lt_mask);
+                r[i] = before + rk;
+                if (rk == 0) s_wcnt[wave][d] = before + (uint32_t)__popcll(peers);
+            }
+        }
+        __syncthreads();
+        uint32_t cnt = 0;
+        if (tid < kRadix) {
+            uint32_t sum = 0;
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) {
+                const uint32_t c = s_wcnt[w][tid];
+                s_wcnt[w][tid] = sum;
+                sum += c;
+            }
+            cnt = sum;
+        }
+        {
+            uint32_t tot;
+            const uint32_t ds = block_exclusive_scan<kSortThreads>(cnt, s_scan, tot);
+            if (tid < kRadix) s_dstart[tid] = ds;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            if (wave * 64 * kSortItems + i * 64 + lane < n) {
+                const uint32_t d = (k[i] >> shift) & (kRadix - 1);
+                const uint32_t p = s_dstart[d] + s_wcnt[wave][d] + r[i];
+                s_keys[p] = k[i];
+                s_vals[p] = v[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const int32_t j = wave * 64 * kSortItems + i * 64 + lane;
+            if (j < n) {
+                k[i] = s_keys[j];
+                v[i] = s_vals[j];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int32_t j = wave * 64 * kSortItems + i * 64 + lane;
+        if (j < n) {
+            keys[j] = k[i];
+            vals[j] = v[i];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- exclusive scan
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__restrict__ data, int32_t len,
@@ -272,6 +365,31 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t *__restrict__ p
         uint32_t tot;
         uint32_t ex = block_exclusive_scan<1024>(v, lds, tot) + carry;
         if (idx < nb) partials[idx] = ex;
+        carry += tot;
+    }
+}
+
+// A short array in one workgroup: chunk by chunk with a running carry (one
+// launch instead of three).
+__global__ __launch_bounds__(kScanThreads) void k_scan_single(uint32_t *__restrict__ data, int32_t len) {
+    __shared__ uint32_t lds[kScanThreads / 64];
+    uint32_t carry = 0;
+    for (int64_t b0 = 0; b0 < len; b0 += kScanTile) {
+        const int64_t base = b0 + (int64_t)threadIdx.x * kScanItems;
+        uint32_t v[kScanItems];
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = (base + k < len) ? data[base + k] : 0u;
+            s += v[k];
+        }
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan<kScanThreads>(s, lds, tot) + carry;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (base + k < len) data[base + k] = ex;
+            ex += v[k];
+        }
         carry += tot;
     }
 }
@@ -304,6 +422,10 @@ int32_t scan_blocks(int32_t len) { return len <= 0 ? 1 : (len + kScanTile - 1) /
 hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, uint32_t *hist,
                              uint32_t *digit_total, int32_t n, int32_t tiles, hipStream_t s) {
     if (n <= 1) return hipSuccess;
+    if (n <= kSortTile) {
+        hipLaunchKernelGGL(k_radix_sort_tile, dim3(1), dim3(kSortThreads), 0, s, keys, vals, n);
+        return hipGetLastError();
+    }
     const int32_t t = radix_tiles(n);
     (void)tiles;
     uint32_t *ki = keys, *vi = vals, *ko = keys2, *vo = vals2;
@@ -352,6 +474,10 @@ hipError_t launch_radix_sort_segmented(uint32_t *keys, uint32_t *vals, uint32_t 
 
 hipError_t launch_exclusive_scan(uint32_t *data, int32_t len, uint32_t *partials, hipStream_t s) {
     if (len <= 0) return hipSuccess;
+    if (len <= 4 * kScanTile) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanThreads), 0, s, data, len);
+        return hipGetLastError();
+    }
     const int32_t nb = scan_blocks(len);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, data, len, partials);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nb);
