@@ -140,12 +140,14 @@ inline int64_t trav_blocks(int64_t n, int32_t ntypes, int32_t block, int32_t qpw
 // Queries per wavefront of a single system.  A wavefront walks the union of
 // its queries' paths, so a small system is faster with fewer queries per
 // wavefront (a smaller union each, more wavefronts in parallel) until there
-// are about two wavefronts per SIMD; a large one keeps all 64 lanes busy.
-// (Measured on LJ fluids of 4000 to 260000 particles: 8 queries up to 30000,
-// 16 at 65000, 32 at 130000, 64 from 260000.)
+// are about two wavefronts per SIMD, and below 8 queries until there is about
+// one; a large one keeps all 64 lanes busy.  (Measured on LJ fluids of 1000 to
+// 260000 particles: 2 queries up to 4000, 8 at 15000 and 30000, 16 at 65000,
+// 32 at 130000, 64 from 260000.)
 inline int32_t queries_per_wave(int64_t n) {
     int32_t q = 64;
     while (q > 8 && (n + q - 1) / q < 2048) q /= 2;
+    while (q > 2 && (n + q - 1) / q < 1024) q /= 2;
     return q;
 }
 
