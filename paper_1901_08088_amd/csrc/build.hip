@@ -302,15 +302,35 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_level(const float4 *__restr
                                                            uint32_t *__restrict__ fcount_out, int32_t *err) {
     __shared__ int32_t s_front[kFrontierCap];
     __shared__ uint32_t s_fcount;
+    __shared__ uint32_t s_off[kFitFanout + 1];
     const int64_t c0 = (int64_t)blockIdx.x * chunk;
     const int64_t c1 = c0 + chunk;
-    if (threadIdx.x == 0) s_fcount = 0;
-    __syncthreads();
     const int32_t j0 = blockIdx.x * kFitFanout;
-    for (int idx = threadIdx.x; idx < kFitFanout * kFrontierCap; idx += kFitThreads) {
-        const int32_t jc = j0 + idx / kFrontierCap;
-        const uint32_t slot = (uint32_t)(idx % kFrontierCap);
-        if (jc >= nprev || slot >= fcount_in[jc]) continue;
+    // The frontier entries of the fan-in chunks, numbered consecutively, so
+    // that each thread climbs from at most a few of them (the climbs are
+    // chains of dependent loads: their count per thread sets the time).
+    if (threadIdx.x < kFitFanout) {
+        const int32_t jc = j0 + (int32_t)threadIdx.x;
+        s_off[threadIdx.x + 1] = jc < nprev ? min(fcount_in[jc], (uint32_t)kFrontierCap) : 0u;
+    }
+    if (threadIdx.x == 0) {
+        s_fcount = 0;
+        s_off[0] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k <= kFitFanout; ++k) s_off[k] += s_off[k - 1];
+    __syncthreads();
+    const uint32_t total = s_off[kFitFanout];
+    for (uint32_t e = threadIdx.x; e < total; e += kFitThreads) {
+        // the chunk k holding entry e: s_off[k] <= e < s_off[k + 1]
+        int lo = 0, hi = kFitFanout;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_off[mid] <= e) lo = mid; else hi = mid;
+        }
+        const int32_t jc = j0 + lo;
+        const uint32_t slot = e - s_off[lo];
         int32_t c = front_in[(int64_t)jc * kFrontierCap + slot];
         int32_t p = c < 0 ? leaf_parent[~c] : parent[c];
         for (int step = 0; p >= 0 && step < kMaxDepth; ++step) {
