@@ -334,32 +334,28 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_level(const float4 *__restr
         int32_t c = front_in[(int64_t)jc * kFrontierCap + slot];
         int32_t p = c < 0 ? leaf_parent[~c] : parent[c];
         for (int step = 0; p >= 0 && step < kMaxDepth; ++step) {
-            if (rf[p] < c0 || rl[p] >= c1) {
+            // The links do not change during the fit: all of them are read
+            // before the atomic, so that a step waits for three round trips
+            // (links, counter, child boxes) rather than five.
+            const int32_t pf = rf[p], pl = rl[p], c0i = left[p], c1i = right[p], pp = parent[p];
+            // (sign bits rather than compares: both loads are then waited for together)
+            if (((uint64_t)((int64_t)pf - c0) | (uint64_t)(c1 - 1 - (int64_t)pl)) >> 63) {
                 frontier_push(c, &s_fcount, s_front, err);
                 break;
             }
             const uint32_t old = __hip_atomic_fetch_add(&visit[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old == 0) break;
-            const int32_t c0i = left[p], c1i = right[p];
-            float4 alo, ahi, blo, bhi;
-            if (c0i < 0) {
-                alo = sorted[~c0i];
-                ahi = alo;
-            } else {
-                alo = box_lo[c0i];
-                ahi = box_hi[c0i];
-            }
-            if (c1i < 0) {
-                blo = sorted[~c1i];
-                bhi = blo;
-            } else {
-                blo = box_lo[c1i];
-                bhi = box_hi[c1i];
-            }
+            // a leaf child's box is its particle: pointers are selected, not
+            // branched on, so the four loads go out together
+            const float4 *pa_lo = c0i < 0 ? sorted + ~c0i : box_lo + c0i;
+            const float4 *pa_hi = c0i < 0 ? sorted + ~c0i : box_hi + c0i;
+            const float4 *pb_lo = c1i < 0 ? sorted + ~c1i : box_lo + c1i;
+            const float4 *pb_hi = c1i < 0 ? sorted + ~c1i : box_hi + c1i;
+            const float4 alo = *pa_lo, ahi = *pa_hi, blo = *pb_lo, bhi = *pb_hi;
             box_lo[p] = make_float4(fminf(alo.x, blo.x), fminf(alo.y, blo.y), fminf(alo.z, blo.z), 0.0f);
             box_hi[p] = make_float4(fmaxf(ahi.x, bhi.x), fmaxf(ahi.y, bhi.y), fmaxf(ahi.z, bhi.z), 0.0f);
             c = p;
-            p = parent[p];
+            p = pp;
         }
     }
     __syncthreads();

@@ -175,6 +175,30 @@ __device__ __forceinline__ void emit_record(int32_t i, int32_t f, int32_t l, con
                                             const float4 *__restrict__ box_lo, const float4 *__restrict__ box_hi,
                                             const uint32_t *__restrict__ P, int32_t leaf_size, int32_t qbits,
                                             uint4 *__restrict__ records, int32_t *__restrict__ ropes) {
+    // Everything that does not depend on the preorder rank is loaded first,
+    // so that those loads overlap the rank climb (a chain of dependent loads).
+    // A leaf child's box is its particle; its range loads read node i's own
+    // entries instead (in bounds, already cached) and are not used.
+    const int32_t ch[2] = {left[i], right[i]};
+    float4 lo[2], hi[2];
+    int32_t cf[2], cl[2];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int32_t c = ch[side];
+        const bool leaf = c < 0;
+        const int32_t k = leaf ? ~c : c;
+        lo[side] = *(leaf ? sorted + k : box_lo + k);
+        hi[side] = *(leaf ? sorted + k : box_hi + k);
+        const int32_t r = leaf ? i : c;
+        const int32_t rfv = rf[r], rlv = rl[r];
+        cf[side] = leaf ? k : rfv;
+        cl[side] = leaf ? k : rlv;
+    }
+    const uint32_t right_rec = P[cf[1]];
+    const int32_t rope = (int32_t)P[l + 1];
+    const int32_t first_rec = (int32_t)P[f];
+    const float root[3] = {m.lo[0], m.lo[1], m.lo[2]};
+    const double h = m.h;
     // preorder position: kept nodes starting before f, plus the ancestors
     // that start at f (the chain of nodes of which i is the left child)
     int32_t rank = 0;
@@ -185,35 +209,25 @@ __device__ __forceinline__ void emit_record(int32_t i, int32_t f, int32_t l, con
         ++rank;
         u = pp;
     }
-    const int32_t at = (int32_t)P[f] + rank;
+    const int32_t at = first_rec + rank;
     const uint32_t qmax = (1u << qbits) - 1u;
     uint32_t w[8];
-    const int32_t ch[2] = {left[i], right[i]};
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-        const int32_t c = ch[side];
-        float4 lo, hi;
+        const int32_t count = cl[side] - cf[side] + 1;
         int32_t ref;
-        if (c < 0) {
-            lo = hi = sorted[~c];
-            ref = run_ref(~c, 1);
-        } else {
-            lo = box_lo[c];
-            hi = box_hi[c];
-            const int32_t cf = rf[c], cl = rl[c];
-            if (cl - cf + 1 > leaf_size)
-                ref = side == 0 ? at + 1 : (int32_t)P[cf];
-            else
-                ref = run_ref(cf, cl - cf + 1);
-        }
-        w[3 * side + 0] = quantize_axis(lo.x, hi.x, m.lo[0], m.h, qmax);
-        w[3 * side + 1] = quantize_axis(lo.y, hi.y, m.lo[1], m.h, qmax);
-        w[3 * side + 2] = quantize_axis(lo.z, hi.z, m.lo[2], m.h, qmax);
+        if (count > leaf_size)
+            ref = side == 0 ? at + 1 : (int32_t)right_rec;
+        else
+            ref = run_ref(cf[side], count);
+        w[3 * side + 0] = quantize_axis(lo[side].x, hi[side].x, root[0], h, qmax);
+        w[3 * side + 1] = quantize_axis(lo[side].y, hi[side].y, root[1], h, qmax);
+        w[3 * side + 2] = quantize_axis(lo[side].z, hi[side].z, root[2], h, qmax);
         w[6 + side] = (uint32_t)ref;
     }
     records[2 * (int64_t)at] = make_uint4(w[0], w[1], w[2], w[3]);
     records[2 * (int64_t)at + 1] = make_uint4(w[4], w[5], w[6], w[7]);
-    ropes[at] = (int32_t)P[l + 1];
+    ropes[at] = rope;
 }
 
 }  // namespace qbi
