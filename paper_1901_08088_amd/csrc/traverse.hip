@@ -110,13 +110,17 @@ __device__ __forceinline__ void flush_ring(Lane &q, int32_t (*s_out)[kBlock], in
     const int s0 = f & (kRing - 1);
     int32_t *row = nbr + ((int64_t)q.orig * max_nbr + f);
     if (kVec4) {
-        // f and max_nbr are multiples of 4 here
-        if (f + 4 <= max_nbr)
-            *reinterpret_cast<int4 *>(row) = make_int4(s_out[s0][threadIdx.x], s_out[s0 + 1][threadIdx.x],
-                                                       s_out[s0 + 2][threadIdx.x], s_out[s0 + 3][threadIdx.x]);
-        if (f + 8 <= max_nbr)
+        // f and max_nbr are multiples of 4 here; one compare covers the usual
+        // case of a row with room for all eight
+        const int4 lo = make_int4(s_out[s0][threadIdx.x], s_out[s0 + 1][threadIdx.x], s_out[s0 + 2][threadIdx.x],
+                                  s_out[s0 + 3][threadIdx.x]);
+        if (f <= max_nbr - 8) {
+            *reinterpret_cast<int4 *>(row) = lo;
             *reinterpret_cast<int4 *>(row + 4) = make_int4(s_out[s0 + 4][threadIdx.x], s_out[s0 + 5][threadIdx.x],
                                                            s_out[s0 + 6][threadIdx.x], s_out[s0 + 7][threadIdx.x]);
+        } else if (f <= max_nbr - 4) {
+            *reinterpret_cast<int4 *>(row) = lo;
+        }
     } else {
 #pragma unroll
         for (int e = 0; e < kFlush; ++e)
@@ -326,7 +330,9 @@ __device__ __forceinline__ void take_run(int32_t ref, bool hit, uint64_t hits, L
                 }
             }
         }
-        if (__any(q.cnt - q.flushed >= kFlush) && q.cnt - q.flushed >= kFlush)
+        // a plain per-lane branch: the wavefront skips it when no lane's
+        // condition holds, with one compare instead of a ballot and a test
+        if (q.cnt - q.flushed >= kFlush)
             flush_ring<kVec4, kBlock>(q, s_out, nbr, max_nbr);
     }
 }

@@ -192,6 +192,18 @@ def test_overflow_keeps_true_counts():
     compare_rows(cfg, nbr, cnt, ovf, 8)
 
 
+@pytest.mark.parametrize("max_nbr", [1, 4, 12, 13, 20, 100])
+def test_overflow_row_ends(max_nbr):
+    """Rows cut at widths that end halfway through an 8-entry flush (4, 12,
+    20 and 100 are 4 mod 8) and at widths that are not a multiple of 4 (the
+    element-store path); with about 140 neighbours per particle every row
+    overflows, so the last partial flush of each row is the one cut."""
+    cfg = W.lj_fluid(4000, seed=7)
+    _, nbr, cnt, ovf = run_nlist(cfg, max_nbr)
+    assert ovf == 1
+    compare_rows(cfg, nbr, cnt, ovf, max_nbr)
+
+
 def test_counts_only():
     cfg = W.lj_fluid(4000)
     _, nbr, cnt, ovf = run_nlist(cfg, 0)
