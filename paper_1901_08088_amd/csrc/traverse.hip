@@ -549,19 +549,26 @@ __device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 
                 const int32_t rope =
                     *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(ropes) + ((uint32_t)v << 2));
                 const bool hl = box_d2(r0.x, r0.y, r0.z, q.ux, q.uy, q.uz, bias) <= q.r2g;
-                const bool hr = box_d2(r0.w, r1.x, r1.y, q.ux, q.uy, q.uz, bias) <= q.r2g;
-                const uint64_t ml = __ballot(hl), mr = __ballot(hr);
-                const bool anyl = ml != 0, anyr = mr != 0;
+                const uint64_t ml = __ballot(hl);
+                const bool anyl = ml != 0;
                 const int32_t cl = (int32_t)r1.z, cr = (int32_t)r1.w;
                 if (cl < 0 && anyl)
                     take_run<kVec4, kBlock, kPaper, kF64>(cl, hl, ml, q, img, a.L, sorted, qpoint, sorted64, nend,
-                                                          s_out, s_src,
-                                                    a.nbr, a.max_nbr);
-                if (cr < 0 && anyr)
-                    take_run<kVec4, kBlock, kPaper, kF64>(cr, hr, mr, q, img, a.L, sorted, qpoint, sorted64, nend,
-                                                          s_out, s_src,
-                                                    a.nbr, a.max_nbr);
-                const int32_t next = (anyl && cl >= 0) ? cl : ((anyr && cr >= 0) ? cr : rope);
+                                                          s_out, s_src, a.nbr, a.max_nbr);
+                // Descending into an internal left child with an internal right
+                // child, the right box is not needed: the walk reaches the right
+                // child's record by the left subtree's rope and tests its
+                // children there (they lie inside its box).
+                int32_t next = cl;
+                if (!(anyl && cl >= 0 && cr >= 0)) {
+                    const bool hr = box_d2(r0.w, r1.x, r1.y, q.ux, q.uy, q.uz, bias) <= q.r2g;
+                    const uint64_t mr = __ballot(hr);
+                    const bool anyr = mr != 0;
+                    if (cr < 0 && anyr)
+                        take_run<kVec4, kBlock, kPaper, kF64>(cr, hr, mr, q, img, a.L, sorted, qpoint, sorted64, nend,
+                                                              s_out, s_src, a.nbr, a.max_nbr);
+                    next = (anyl && cl >= 0) ? cl : ((anyr && cr >= 0) ? cr : rope);
+                }
                 // references always point forward; max() makes progress unconditional
                 v = uniform(max(next, v + 1));
             }
