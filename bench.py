@@ -92,13 +92,13 @@ def traversal_bytes(n: int, nrecords: int, stored_pairs: int) -> int:
 # factor the same counters read for a plain elementwise copy of known size (the
 # --copy-probe-mib kernel).  Valid only for the kernel sources it was taken on:
 # ``traffic`` is reported as null once their hash differs.
-TRAFFIC = {"sources": "df3eb8d54f5e9306", "workload": "lj8m",
+TRAFFIC = {"sources": "2882763f409fd6ad", "workload": "lj8m",
            "opts": {"leaf_size": 16, "qbits": 16, "block_size": 64},
-           "fetch_kib": 1589888.13, "write_kib": 6636852.42, "copy_factor": 1.0,
-           "fetch_factor": 0.500024, "profile": "profiles/k_traverse_lj8m_counters.md",
+           "fetch_kib": 1611209.25, "write_kib": 6669795.15, "copy_factor": 1.0,
+           "fetch_factor": 0.500017, "profile": "profiles/k_traverse_lj8m_counters.md",
            # SQ_ACTIVE_INST_VALU / (SIMDs x kernel cycles / 4): the VALU issues one wave64
            # instruction per 4 cycles per SIMD, so this is the kernel's VALU issue roofline
-           "valu_busy": 0.91}
+           "valu_busy": 0.89}
 KERNEL_SOURCES = ("paper_1901_08088_amd/csrc/traverse.hip", "paper_1901_08088_amd/csrc/qbvh_internal.h")
 
 
