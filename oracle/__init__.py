@@ -54,6 +54,9 @@ def configure(lib):
     lib.oracle_pair_d2.restype = ctypes.c_double
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_band_count.argtypes = [I64, P, P, I32, P, P, I64, P, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int, P, P, ctypes.c_int]
+    lib.oracle_band_count.restype = ctypes.c_int
     return lib
 
 
@@ -177,16 +180,35 @@ def pair_d2(pi, pj, box) -> float:
     return float(lib.oracle_pair_d2(_ptr(a), _ptr(b), _ptr(L)))
 
 
-def band_pairs(pos, box, rcut, skin, row_ptr, cols, queries=None, types=None, rel: float = 1e-5):
-    """Number of listed pairs whose distance lies within ``rel * r_list`` of the list radius."""
-    pos, L = _as_f64(pos, box)
-    r2 = rlist2_table(rcut, skin)
-    qi = np.arange(row_ptr.shape[0] - 1) if queries is None else np.asarray(queries)
-    rows = np.repeat(qi, np.diff(row_ptr))
-    d = pos[cols] - pos[rows]
-    d = d - L * np.round(d / L)
-    dist = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
-    ti = np.zeros(rows.shape[0], np.int64) if types is None else np.asarray(types)[rows]
-    tj = np.zeros(rows.shape[0], np.int64) if types is None else np.asarray(types)[cols]
-    r = np.sqrt(np.maximum(r2[ti, tj], 0.0))
-    return int(np.count_nonzero(np.abs(dist - r) <= rel * r))
+def band_counts(pos, box, rcut, skin, types=None, queries=None, rel: float = 1e-5,
+                abs_tol: float = 1e-5, method: str = "auto", nthreads: int = 0):
+    """Per query, the number of partners j != i (listed type pairs only) whose
+    fp64 minimum-image distance lies within the band around the list radius r,
+    under the two readings of a 1e-5 tolerance: ``|d - r| <= rel * r``
+    (relative) and ``|d - r| <= abs_tol`` (absolute, in sigma).
+
+    Both arrays are int64 [nq].  These are the pairs where a distance computed
+    in another floating-point order may fall on the other side of eq. (2)'s
+    inclusive test.  ``method``: "brute", "cells" or "auto" (cells unless the
+    box is too small for a 3-cell stencil at the widened radius).
+    """
+    lib = _load()
+    pos, box64, r2, ntypes, t = _prep(pos, box, rcut, skin, types)
+    n = pos.shape[0]
+    q = None if queries is None else np.ascontiguousarray(queries, dtype=np.int64)
+    nq = n if q is None else q.shape[0]
+    a = np.zeros(max(nq, 1), dtype=np.int64)
+    b = np.zeros(max(nq, 1), dtype=np.int64)
+    rc = 1
+    if method in ("auto", "cells"):
+        rc = lib.oracle_band_count(n, _ptr(pos), _ptr(t), ntypes, _ptr(box64), _ptr(r2), nq, _ptr(q),
+                                   float(rel), float(abs_tol), 1, _ptr(a), _ptr(b), nthreads)
+        if rc == 1 and method == "cells":
+            raise ValueError("box too small for a 3x3x3 cell stencil")
+        if rc < 0:
+            raise RuntimeError("oracle_band_count failed")
+    if rc == 1:
+        if lib.oracle_band_count(n, _ptr(pos), _ptr(t), ntypes, _ptr(box64), _ptr(r2), nq, _ptr(q),
+                                 float(rel), float(abs_tol), 0, _ptr(a), _ptr(b), nthreads) != 0:
+            raise RuntimeError("oracle_band_count failed")
+    return a[:nq], b[:nq]

@@ -304,3 +304,98 @@ double oracle_pair_d2(const double *pi, const double *pj, const double *box)
 {
     return pair_d2(pi, pj, box);
 }
+
+/* ----------------------------------------------------------------- band pairs */
+
+/* Pairs near the cutoff, where a floating-point evaluation of the distance in
+ * another order can take the other side of eq. (2)'s inclusive test.  For each
+ * query i and each j != i of a listed type pair (r = sqrt(rlist2) > 0):
+ *   rel_count[q] += |d_ij - r| <= rel * r      (relative reading)
+ *   abs_count[q] += |d_ij - r| <= abs_tol      (absolute reading, sigma units)
+ * with d_ij = sqrt(d_ij^2) of the definition above.  Candidates come from a
+ * cell list whose cells are at least max(r (1 + rel), r + abs_tol) wide, or,
+ * with use_cells = 0, from every pair. */
+static double band_reach(int32_t ntypes, const double *rlist2, double rel, double abs_tol)
+{
+    double m = 0.0;
+    for (int32_t k = 0; k < ntypes * ntypes; ++k) {
+        if (!(rlist2[k] > 0.0))
+            continue;
+        double r = sqrt(rlist2[k]);
+        double a = r * (1.0 + rel), b = r + abs_tol;
+        double e = a > b ? a : b;
+        if (e > m)
+            m = e;
+    }
+    return m;
+}
+
+static void band_pair(const double *pi, const double *pj, const double *box, double r2,
+                      double rel, double abs_tol, int64_t *nrel, int64_t *nabs)
+{
+    if (!(r2 > 0.0))
+        return;
+    double r = sqrt(r2);
+    double dev = fabs(sqrt(pair_d2(pi, pj, box)) - r);
+    if (dev <= rel * r)
+        ++*nrel;
+    if (dev <= abs_tol)
+        ++*nabs;
+}
+
+int oracle_band_count(int64_t n, const double *pos, const int32_t *type, int32_t ntypes,
+                      const double *box, const double *rlist2, int64_t nq, const int64_t *queries,
+                      double rel, double abs_tol, int use_cells, int64_t *rel_count,
+                      int64_t *abs_count, int nthreads)
+{
+    if (n < 0 || nq < 0 || !box || !rlist2 || !rel_count || !abs_count || (n > 0 && !pos) ||
+        !(rel >= 0.0) || !(abs_tol >= 0.0))
+        return -1;
+    set_threads(nthreads);
+    cells_t g;
+    int ok = 0;
+    if (use_cells) {
+        ok = cells_build(&g, n, pos, box, band_reach(ntypes, rlist2, rel, abs_tol));
+        if (ok < 0)
+            return -1;
+        if (ok == 0)
+            return 1;
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t q = 0; q < nq; ++q) {
+        int64_t i = queries ? queries[q] : q;
+        int ti = type_of(type, i);
+        int64_t a = 0, b = 0;
+        if (!use_cells) {
+            for (int64_t j = 0; j < n; ++j)
+                if (j != i)
+                    band_pair(pos + 3 * i, pos + 3 * j, box, rlist2[ti * ntypes + type_of(type, j)],
+                              rel, abs_tol, &a, &b);
+        } else {
+            int64_t c0 = cell_coord((double)pos[3 * i + 0], g.width[0], g.nc[0]);
+            int64_t c1 = cell_coord((double)pos[3 * i + 1], g.width[1], g.nc[1]);
+            int64_t c2 = cell_coord((double)pos[3 * i + 2], g.width[2], g.nc[2]);
+            for (int dz = -1; dz <= 1; ++dz) {
+                int64_t z = (c2 + dz + g.nc[2]) % g.nc[2];
+                for (int dy = -1; dy <= 1; ++dy) {
+                    int64_t y = (c1 + dy + g.nc[1]) % g.nc[1];
+                    for (int dxc = -1; dxc <= 1; ++dxc) {
+                        int64_t x = (c0 + dxc + g.nc[0]) % g.nc[0];
+                        int64_t cell = (z * g.nc[1] + y) * g.nc[0] + x;
+                        for (int64_t s = g.start[cell]; s < g.start[cell + 1]; ++s) {
+                            int64_t j = g.item[s];
+                            if (j != i)
+                                band_pair(pos + 3 * i, pos + 3 * j, box,
+                                          rlist2[ti * ntypes + type_of(type, j)], rel, abs_tol, &a, &b);
+                        }
+                    }
+                }
+            }
+        }
+        rel_count[q] = a;
+        abs_count[q] = b;
+    }
+    if (use_cells)
+        cells_free(&g);
+    return 0;
+}

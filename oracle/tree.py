@@ -18,29 +18,22 @@ Section 2.2, "Compressed BVH"):
 4. ``node_boxes``    -- axis-aligned box of every internal node, i.e. the
                          min/max over the particles below it (what the
                          bottom-up fit computes).
-5. ``record_layout`` -- quantized nodes in a stackless, rope-linked order:
-                         bounds snapped to a grid over the root-node box,
-                         lower bounds rounded down and upper bounds up, and a
-                         rope per node giving the next node to test when
-                         nothing below it needs visiting.
+5. ``grid_spacing`` and ``quantize_box`` -- the root-node box of a tree
+                         divided into 2^b - 1 bins along each axis; a box's
+                         lower bounds rounded down and upper bounds rounded up
+                         onto that grid (Section 2.2; Section 3 for the
+                         directed rounding).
+
+How a quantized tree is laid out in memory (node size, child and rope
+encoding) is a design choice of an implementation, not part of the method;
+it is not defined here.
 
 Readings where the paper is silent (listed again in the design notes):
 - One tree per particle type; the type is stored above the 30-bit code
   (bits 30-31) so one sort groups the types.
-- The grid is isotropic: one bin width h = extent / (2^b - 1) for all axes,
-  where extent is the largest edge of the root-node box (floored at 2^-24 of
-  the largest periodic box edge so that a tree of coincident points still has
-  a usable grid).  Bounds are stored in 16-bit fields for any b <= 16.
-- Nodes are laid out as two-wide records in depth-first preorder: the record
-  of an internal node holds the quantized boxes of its two children and a
-  reference to each (the record of an internal child, or a run of at most
-  ``leaf_size`` consecutive sorted particles: a subtree that small is not
-  split further), and a separate array holds its rope (the record after its
-  subtree).  The left child's record is the next record.  Testing both child
-  boxes in the parent halves the chain of dependent node loads of a walk.
-- A particle-run reference is ~((first << 4) | (count - 1)), negative; a
-  record reference is the record index, non-negative.  A tree of at most
-  ``leaf_size`` particles has no record: its root is a run.
+- An axis along which the root-node box has no extent (all of the tree's
+  particles share that coordinate) still gets a grid: its extent is floored
+  at 2^-24 of the largest periodic box edge.
 """
 from __future__ import annotations
 
@@ -126,97 +119,43 @@ def node_boxes(sorted_pos, nodes: dict) -> dict:
     return {(f, l): (p[f:l + 1].min(axis=0), p[f:l + 1].max(axis=0)) for (f, l) in nodes}
 
 
-def grid_spacing(lo, hi, box, qbits: int) -> float:
-    """Isotropic bin width over the root-node box [lo, hi] (fp64)."""
-    ext = max(float(np.float64(hi[d]) - np.float64(lo[d])) for d in range(3))
+def grid_spacing(lo, hi, box, qbits: int) -> np.ndarray:
+    """Bin width along each axis of the grid over the root-node box [lo, hi]:
+    h_d = extent_d / (2^b - 1) in fp64, with extent_d floored at 2^-24 of the
+    largest periodic box edge (fp64 array of 3)."""
     floor_ext = float(np.max(np.asarray(box, dtype=np.float32).astype(np.float64))) * 2.0 ** -24
-    ext = max(ext, floor_ext)
-    return ext / float((1 << qbits) - 1)
+    h = np.empty(3, np.float64)
+    for d in range(3):
+        ext = float(np.float64(hi[d])) - float(np.float64(lo[d]))
+        h[d] = max(ext, floor_ext) / float((1 << qbits) - 1)
+    return h
 
 
-def quantize_box(lo, hi, root_lo, h: float, qbits: int):
+def quantize_box(lo, hi, root_lo, h, qbits: int):
     """Grid coordinates of a box: lower bounds rounded down, upper bounds up.
 
-    q_lo = floor((lo - root_lo) / h), q_hi = ceil((hi - root_lo) / h), both
-    evaluated in fp64 and clamped to [0, 2^qbits - 1].
+    q_lo = floor((lo - root_lo) / h_d), q_hi = ceil((hi - root_lo) / h_d),
+    both evaluated in fp64 and clamped to [0, 2^qbits - 1].  ``h`` is the bin
+    width of each axis (a scalar is taken for all three).
     """
     qmax = (1 << qbits) - 1
+    hd = np.broadcast_to(np.asarray(h, dtype=np.float64), (3,))
     qlo, qhi = [], []
     for d in range(3):
-        tl = (float(np.float64(lo[d])) - float(np.float64(root_lo[d]))) / h
-        th = (float(np.float64(hi[d])) - float(np.float64(root_lo[d]))) / h
+        tl = (float(np.float64(lo[d])) - float(np.float64(root_lo[d]))) / float(hd[d])
+        th = (float(np.float64(hi[d])) - float(np.float64(root_lo[d]))) / float(hd[d])
         qlo.append(int(min(max(np.floor(tl), 0), qmax)))
         qhi.append(int(min(max(np.ceil(th), 0), qmax)))
     return qlo, qhi
 
 
-def run_ref(first: int, count: int) -> int:
-    """Reference to the particle run [first, first + count) (negative int32)."""
-    return ~((first << 4) | (count - 1))
-
-
-def record_layout(sorted_pos, sorted_keys, ntypes: int, box, leaf_size: int = 1, qbits: int = 16):
-    """Two-wide quantized records for all types' trees.
-
-    Returns (records uint32 [M, 8], ropes int32 [M], meta list).  Record of
-    internal node v with children a (left) and b (right):
-      words 0-2: box of a, w_d = q_lo_d | (q_hi_d << 16) for d = x, y, z
-      words 3-5: box of b, same packing
-      word 6:    reference to a;  word 7: reference to b
-    ropes[v] = index of the record that follows v's subtree.  Trees follow
-    each other in type order; ``meta[t]`` holds the tree's root reference,
-    one past its last record, its root box and its grid spacing.
-    """
-    assert 1 <= leaf_size <= 16
-    p = np.asarray(sorted_pos, dtype=np.float32).reshape(-1, 3)
-    records, ropes, meta = [], [], []
-    for t, (s, e) in enumerate(segments(sorted_keys, ntypes)):
-        first = len(records)
-        if e == s:
-            meta.append(dict(start=s, count=0, root=0, end=first, lo=None, hi=None, h=1.0))
-            continue
-        tree = radix_tree(sorted_keys, s, e)
-        rlo = p[s:e].min(axis=0)
-        rhi = p[s:e].max(axis=0)
-        h = grid_spacing(rlo, rhi, box, qbits)
-        if e - s <= leaf_size:
-            meta.append(dict(start=s, count=e - s, root=run_ref(s, e - s), end=first, lo=rlo, hi=rhi, h=h))
-            continue
-
-        def child_box(f, l):
-            qlo, qhi = quantize_box(p[f:l + 1].min(axis=0), p[f:l + 1].max(axis=0), rlo, h, qbits)
-            return [qlo[d] | (qhi[d] << 16) for d in range(3)]
-
-        def emit(f, l):
-            """Record of node [f, l] in preorder: itself, then its left and right subtrees."""
-            idx = len(records)
-            g = tree[(f, l)]
-            kids = [(f, g), (g + 1, l)]
-            records.append(child_box(*kids[0]) + child_box(*kids[1]) + [0, 0])
-            ropes.append(-1)
-            for side, (cf, cl) in enumerate(kids):
-                if cl - cf + 1 > leaf_size:
-                    ref = emit(cf, cl)
-                else:
-                    ref = run_ref(cf, cl - cf + 1)
-                records[idx][6 + side] = ref & 0xFFFFFFFF
-            ropes[idx] = len(records)
-            return idx
-
-        emit(s, e - 1)
-        meta.append(dict(start=s, count=e - s, root=first, end=len(records), lo=rlo, hi=rhi, h=h))
-    arr = np.array(records, dtype=np.uint32).reshape(-1, 8) if records else np.zeros((0, 8), np.uint32)
-    return arr, np.array(ropes, dtype=np.int32), meta
-
-
-def build_all(pos, box, types=None, ntypes: int = 1, leaf_size: int = 1, qbits: int = 16):
-    """Run every step; returns a dict with each intermediate result."""
+def build_steps(pos, box, types=None, ntypes: int = 1):
+    """Run steps 1-4; returns a dict with each intermediate result."""
     keys = morton_keys(pos, box, types)
     skeys, perm = sort_keys(keys)
     p = np.asarray(pos, dtype=np.float32).reshape(-1, 3)[perm]
     segs = segments(skeys, ntypes)
     trees = [radix_tree(skeys, s, e) for (s, e) in segs]
     boxes = [node_boxes(p, tr) for tr in trees]
-    records, ropes, meta = record_layout(p, skeys, ntypes, box, leaf_size, qbits)
     return dict(keys=keys, sorted_keys=skeys, perm=perm, sorted_pos=p, segments=segs,
-                trees=trees, boxes=boxes, records=records, ropes=ropes, meta=meta)
+                trees=trees, boxes=boxes)

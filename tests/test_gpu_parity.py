@@ -14,6 +14,8 @@ import paper_1901_08088_amd as Q
 import workloads as W
 from oracle import tree as T
 
+import layout_ref as LR
+
 from nlist_check import compare_rows, export, require_gpu, run_nlist, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -23,7 +25,7 @@ def _step_parity(cfg, leaf_size=1, qbits=16):
     torch = require_gpu()
     pos, types = to_dev(cfg)
     tree = Q.qbvh_build(pos, types, cfg.box, cfg.ntypes, {"leaf_size": leaf_size, "qbits": qbits})
-    ref = T.build_all(cfg.pos, cfg.box, types=cfg.types, ntypes=cfg.ntypes, leaf_size=leaf_size, qbits=qbits)
+    ref = LR.build_all(cfg.pos, cfg.box, types=cfg.types, ntypes=cfg.ntypes, leaf_size=leaf_size, qbits=qbits)
     n = cfg.n
     info = Q.qbvh_info(tree)
     keys = export(tree, "keys", n, torch.int32).view(np.uint32)

@@ -31,6 +31,13 @@ MUTANTS = {
     "sign_error": ("(double)pj[d] - (double)pi[d]", "(double)pj[d] + (double)pi[d]"),
     "half_stencil": ("for (int dz = -1; dz <= 1; ++dz)", "for (int dz = 0; dz <= 1; ++dz)"),
     "narrow_cells": ("double w = rmax * (1.0 + 1e-9);", "double w = rmax * 0.75;"),
+    # band-pair counting
+    "band_not_relative": ("if (dev <= rel * r)", "if (dev <= rel)"),
+    "band_one_sided": ("double dev = fabs(sqrt(pair_d2(pi, pj, box)) - r);",
+                       "double dev = sqrt(pair_d2(pi, pj, box)) - r;"),
+    "band_squared": ("double dev = fabs(sqrt(pair_d2(pi, pj, box)) - r);",
+                     "double dev = fabs(pair_d2(pi, pj, box) - r2);"),
+    "band_reach_unwidened": ("double e = a > b ? a : b;", "double e = r;"),
 }
 
 
@@ -88,6 +95,23 @@ def _pins_pass() -> bool:
             return False
         expect = 0.85 * (4.0 / 3.0) * math.pi * 3.4 ** 3
         if abs(np.diff(a[0]).mean() / expect - 1.0) >= 0.015:
+            return False
+        # band pairs: one pair 5e-6 r inside and one 5e-6 r outside the list radius
+        # (both in the relative band), one 2e-5 r outside (in neither band)
+        r = float(np.float32(3.0)) + float(np.float32(0.4))
+        pb = []
+        for k, rel in enumerate((-5e-6, 5e-6, 2e-5)):
+            pb += [[5.0 + 8.0 * k, 9.0, 9.0], [5.0 + 8.0 * k, 9.0, 9.0 + r * (1.0 + rel)]]
+        for method in ("brute", "cells"):
+            ra, rb = oracle.band_counts(np.array(pb), np.array([30.0, 30.0, 30.0]), [[3.0]], 0.4,
+                                        method=method)
+            if ra.tolist() != [1, 1, 1, 1, 0, 0] or rb.tolist() != [0] * 6:
+                return False
+        # a band pair just outside r whose points lie two list-radius cells apart
+        w = r * (1.0 + 1e-8)
+        pc = np.array([[5.0, 5.0, w - 1e-7], [5.0, 5.0, w - 1e-7 + r * (1.0 + 5e-6)]])
+        ra, _ = oracle.band_counts(pc, np.array([30.0, 30.0, 9.0 * w]), [[3.0]], 0.4, method="cells")
+        if ra.tolist() != [1, 1]:
             return False
     except (ValueError, RuntimeError, IndexError):
         return False

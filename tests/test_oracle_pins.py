@@ -260,3 +260,77 @@ def test_fp64_lists_differ_from_their_fp32_rounding_only_near_the_cutoff():
         for j in a[i] ^ b[i]:
             d = math.sqrt(oracle.pair_d2(pos64[i], pos64[j], box64))
             assert abs(d - R) < 1e-5, (i, j, d)
+
+
+# ------------------------------------------------------------------ band pairs
+
+def _r_list(rc, skin):
+    return float(np.float32(rc)) + float(np.float32(skin))
+
+
+@pytest.mark.parametrize("method", ["brute", "cells"])
+def test_band_counts_hand_pairs(method):
+    # fp64 points, so each pair sits at an exactly placed distance from r = rc + skin;
+    # relative band 1e-5 * r = 3.4e-5, absolute band 1e-5
+    r = _r_list(3.0, 0.4)
+    box = np.array([40.0, 40.0, 40.0])
+    # relative offsets of the five pairs: the first two inside the relative band,
+    # the other three outside it (2e-5 r = 6.8e-5 > 3.4e-5)
+    offs = [+5e-6, -5e-6, +2e-5, -2e-5, +1e-4]
+    pos = []
+    for k, rel in enumerate(offs):
+        base = np.array([5.0 + 7.0 * k, 20.0, 20.0])
+        pos += [base, base + np.array([0.0, r * (1.0 + rel), 0.0])]
+    pos = np.array(pos)
+    a, b = oracle.band_counts(pos, box, [[3.0]], 0.4, method=method)
+    assert a.tolist() == [1, 1, 1, 1, 0, 0, 0, 0, 0, 0]
+    # absolute: |d - r| = 1.7e-5 sigma for the first two pairs, above 1e-5: out
+    assert b.tolist() == [0] * 10
+    # a pair 0.5e-5 sigma outside r is in both bands; 2e-5 sigma outside is in the
+    # relative band only (2e-5 < 3.4e-5)
+    pos = np.array([[5.0, 5.0, 5.0], [5.0, 5.0, 5.0 + r + 0.5e-5],
+                    [20.0, 5.0, 5.0], [20.0, 5.0, 5.0 + r + 2e-5]])
+    a, b = oracle.band_counts(pos, box, [[3.0]], 0.4, method=method)
+    assert a.tolist() == [1, 1, 1, 1] and b.tolist() == [1, 1, 0, 0]
+
+
+def test_band_counts_reach_past_the_list_radius_cells():
+    # cells exactly one list radius wide (9 along z): the pair sits 5e-6 r outside r
+    # with its points two such cells apart, so the cells must be widened for the band
+    r = _r_list(3.0, 0.4)
+    w = r * (1.0 + 1e-8)
+    pos = np.array([[5.0, 5.0, w - 1e-7], [5.0, 5.0, w - 1e-7 + r * (1.0 + 5e-6)]])
+    box = np.array([30.0, 30.0, 9.0 * w])
+    for method in ("brute", "cells"):
+        a, _ = oracle.band_counts(pos, box, [[3.0]], 0.4, method=method)
+        assert a.tolist() == [1, 1]
+
+
+def test_band_counts_across_a_face_and_type_pairs():
+    r = _r_list(1.0, 0.25)
+    box = np.array([12.0, 12.0, 12.0])
+    # a band pair across the x face, and a band pair of a disabled type pair
+    pos = np.array([[0.2, 6.0, 6.0], [12.0 - (r * (1 + 2e-6) - 0.2), 6.0, 6.0],
+                    [6.0, 2.0, 2.0], [6.0, 2.0, 2.0 + r]])
+    types = np.array([0, 0, 1, 1], np.int32)
+    rc = np.array([[1.0, 1.0], [1.0, 0.0]], np.float32)
+    for method in ("brute", "cells"):
+        a, b = oracle.band_counts(pos, box, rc, 0.25, types=types, method=method)
+        assert a.tolist() == [1, 1, 0, 0] and b.tolist() == [1, 1, 0, 0]
+
+
+def test_band_counts_brute_equals_cells_and_poisson_mean():
+    # ideal gas: the expected band pairs per particle are rho * 4 pi r^2 * 2 rel r
+    pos, box = W.uniform(6000, [30.0, 30.0, 30.0], seed=21)
+    rel = 1e-3  # wide enough that the count is large
+    a1, b1 = oracle.band_counts(pos, box, [[3.0]], 0.4, rel=rel, abs_tol=2e-3, method="brute")
+    a2, b2 = oracle.band_counts(pos, box, [[3.0]], 0.4, rel=rel, abs_tol=2e-3, method="cells")
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+    r = _r_list(3.0, 0.4)
+    rho = 6000 / 27000.0
+    mean_rel = rho * 4 * math.pi * r * r * 2 * rel * r * 5999 / 6000
+    mean_abs = rho * 4 * math.pi * r * r * 2 * 2e-3 * 5999 / 6000
+    for got, mean in ((a1.sum(), mean_rel), (b1.sum(), mean_abs)):
+        # directed pairs: each unordered pair twice, so the variance is 2 * mean * N
+        sd = math.sqrt(2.0 * mean * 6000)
+        assert abs(got - mean * 6000) < 6 * sd, (got, mean * 6000)

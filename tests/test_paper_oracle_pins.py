@@ -41,7 +41,7 @@ def test_cell_boxes_contain_points_and_span_one_cell():
     lo, hi, h = P.cell_boxes(cfg.pos, cfg.box, None, 1, 10)
     x = cfg.pos.astype(np.float64)
     assert np.all(lo <= x) and np.all(x <= hi)
-    assert np.all(hi - lo <= h[:, None] * (1 + 1e-12))
+    assert np.all(hi - lo <= h * (1 + 1e-12))
 
 
 @pytest.mark.parametrize("qbits", [8, 10])
@@ -65,8 +65,45 @@ def test_false_positives_match_the_closed_form(qbits):
     erp, _ = oracle.neighbor_lists(pos, box, rcut, 0.4)
     fp = float((np.diff(rp) - np.diff(erp)).mean())
     _, _, h = P.cell_boxes(pos, box, None, 1, qbits)
-    want = P.false_positive_mean(n / float(np.prod(box.astype(np.float64))), 3.4, float(h[0]))
+    want = P.false_positive_mean(n / float(np.prod(box.astype(np.float64))), 3.4, h[0])
     assert abs(fp - want) <= 0.25 * want, (fp, want)
+
+
+def test_bins_are_per_axis_on_a_long_box():
+    # root box about 10 x 10 x 40: 8-bit bins of about 0.039, 0.039 and 0.157 sigma.
+    # The false positives follow the per-axis closed form (Steiner's formula for a
+    # 0.039 x 0.039 x 0.157 box) and are about half of what one 0.157 bin would give.
+    n = 2000
+    pos, box = W.uniform(n, [10.0, 10.0, 40.0], 4343)
+    rcut = np.array([[1.6]], np.float32)
+    rp, _ = P.paper_lists(pos, box, rcut, 0.4, qbits=8)
+    erp, _ = oracle.neighbor_lists(pos, box, rcut, 0.4)
+    fp = float((np.diff(rp) - np.diff(erp)).mean())
+    _, _, h = P.cell_boxes(pos, box, None, 1, 8)
+    assert h[0, 2] > 3.5 * h[0, 0] and abs(h[0, 0] - h[0, 1]) < 0.01 * h[0, 0]
+    rho = n / 4000.0
+    R = float(np.float32(1.6)) + float(np.float32(0.4))
+    want = P.false_positive_mean(rho, R, h[0])
+    iso = P.false_positive_mean(rho, R, h[0].max())
+    assert abs(fp - want) <= 0.25 * want and fp < 0.7 * iso, (fp, want, iso)
+
+
+def test_per_axis_bins_hand_pair():
+    # root box [1, 11] x [1, 11] x [1, 41] (particles 0 and 1 at opposite corners),
+    # 8 bits: h_x = 10/255 = 0.0392, h_z = 40/255 = 0.1569; R = 3.0 + 0.42.
+    # Along x, particle 3 is 3.46 from particle 2 and its cell starts at
+    # 1 + 139 h_x = 6.451, 3.451 away: not listed (one 0.1569 bin on every axis
+    # would put the face at 6.333 and list it).  Along z, particle 5 is 3.43 from
+    # particle 4 and its cell starts at 1 + 79 h_z = 13.392, 3.392 away: listed.
+    pos = np.array([[1.0, 1.0, 1.0], [11.0, 11.0, 41.0], [3.0, 6.0, 20.0], [6.46, 6.0, 20.0],
+                    [6.0, 3.0, 10.0], [6.0, 3.0, 13.43]], np.float32)
+    box = np.array([30.0, 30.0, 60.0], np.float32)
+    rp, cols = P.paper_lists(pos, box, [[3.0]], 0.42, qbits=8)
+    assert 3 not in cols[rp[2]:rp[3]]
+    assert 5 in cols[rp[4]:rp[5]]
+    lo, hi, h = P.cell_boxes(pos, box, None, 1, 8)
+    assert np.allclose(h[0], [10 / 255, 10 / 255, 40 / 255], rtol=1e-12)
+    assert abs(lo[3, 0] - (1 + 139 * 10 / 255)) < 1e-12 and abs(lo[5, 2] - (1 + 79 * 40 / 255)) < 1e-12
 
 
 def test_paper_figure_reproduced_by_the_closed_form():

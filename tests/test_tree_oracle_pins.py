@@ -16,6 +16,8 @@ import oracle
 import workloads as W
 from oracle import tree as T
 
+import layout_ref as LR
+
 
 # ------------------------------------------------------------------- Morton codes
 
@@ -119,7 +121,7 @@ def test_radix_tree_on_segment_offset():
 
 def test_boxes_union_and_root():
     cfg = W.lj_fluid(1500, seed=4)
-    b = T.build_all(cfg.pos, cfg.box)
+    b = T.build_steps(cfg.pos, cfg.box)
     (tree,), (boxes,) = b["trees"], b["boxes"]
     p = b["sorted_pos"]
 
@@ -139,17 +141,19 @@ def test_boxes_union_and_root():
 
 @pytest.mark.parametrize("qbits", [10, 16])
 def test_quantized_bounds_are_outward_and_within_one_bin(qbits):
-    cfg = W.lj_fluid(800, seed=6)
-    b = T.build_all(cfg.pos, cfg.box, qbits=qbits)
+    # a root box with unequal edges, so each axis has its own bin width
+    pos, box = W.uniform(800, [9.0, 14.0, 23.0], seed=6)
+    b = T.build_steps(pos, box)
     (boxes,) = b["boxes"]
-    rlo, rhi = boxes[(0, cfg.n - 1)]
-    h = T.grid_spacing(rlo, rhi, cfg.box, qbits)
-    assert h * ((1 << qbits) - 1) >= float(np.max(rhi.astype(np.float64) - rlo.astype(np.float64)))
-    H = Fraction(h)
+    rlo, rhi = boxes[(0, 799)]
+    h = T.grid_spacing(rlo, rhi, box, qbits)
+    ext = rhi.astype(np.float64) - rlo.astype(np.float64)
+    assert np.all(h * ((1 << qbits) - 1) >= ext) and h[0] < h[1] < h[2]
     tol = Fraction(1, 10 ** 9)  # fp64 evaluation error, far below the traversal's 2-bin pad
     for (f, l), (lo, hi) in list(boxes.items())[:300]:
         qlo, qhi = T.quantize_box(lo, hi, rlo, h, qbits)
         for d in range(3):
+            H = Fraction(float(h[d]))
             assert 0 <= qlo[d] <= qhi[d] <= (1 << qbits) - 1
             glo = (Fraction(float(lo[d])) - Fraction(float(rlo[d]))) / H
             ghi = (Fraction(float(hi[d])) - Fraction(float(rlo[d]))) / H
@@ -157,10 +161,32 @@ def test_quantized_bounds_are_outward_and_within_one_bin(qbits):
             assert qlo[d] > glo - 1 and qhi[d] < ghi + 1              # at most one bin loose
 
 
+def test_per_axis_bins_hand_values():
+    # root box [0,2] x [0,4] x [0,8] with 2-bit bounds: 3 bins per axis of
+    # widths 2/3, 4/3 and 8/3; the point (1,1,1) lies in bins 1, 0 and 0
+    lo = np.zeros(3, np.float32)
+    hi = np.array([2.0, 4.0, 8.0], np.float32)
+    h = T.grid_spacing(lo, hi, np.full(3, 10.0, np.float32), 2)
+    assert np.allclose(h, [2 / 3, 4 / 3, 8 / 3], rtol=0, atol=1e-15)
+    p = np.ones(3, np.float32)
+    assert T.quantize_box(p, p, lo, h, 2) == ([1, 0, 0], [2, 1, 1])
+    assert T.quantize_box(lo, hi, lo, h, 2) == ([0, 0, 0], [3, 3, 3])  # the root box spans every bin
+
+
 def test_grid_spacing_floor_for_coincident_points():
     lo = hi = np.array([1.0, 2.0, 3.0], np.float32)
     h = T.grid_spacing(lo, hi, np.full(3, 10.0, np.float32), 16)
-    assert h == 10.0 * 2.0 ** -24 / 65535
+    assert np.all(h == 10.0 * 2.0 ** -24 / 65535)
+    # only the axis without extent is floored
+    h = T.grid_spacing(lo, np.array([1.0, 5.0, 3.0], np.float32), np.full(3, 10.0, np.float32), 16)
+    assert h[1] == 3.0 / 65535 and h[0] == h[2] == 10.0 * 2.0 ** -24 / 65535
+
+
+def test_layout_grid_is_the_largest_axis_width():
+    # the library's isotropic grid (layout helper) takes the largest per-axis width
+    lo = np.zeros(3, np.float32)
+    hi = np.array([2.0, 7.0, 3.0], np.float32)
+    assert LR.iso_spacing(lo, hi, np.full(3, 10.0, np.float32), 10) == 7.0 / 1023
 
 
 # --------------------------------------------------- layout: Algorithm 1 on the CPU
@@ -242,7 +268,7 @@ def _alg1_rows(records, ropes, meta, box, rlist2, qtypes, qpos, orig_of_query, s
 @pytest.mark.parametrize("leaf_size,qbits", [(1, 16), (1, 10), (3, 16), (8, 12), (16, 16), (13, 10)])
 def test_layout_traversal_reproduces_brute_force(leaf_size, qbits):
     cfg = W.lj_fluid(350, seed=8, rho=0.6, rc=2.0, skin=0.3)
-    b = T.build_all(cfg.pos, cfg.box, leaf_size=leaf_size, qbits=qbits)
+    b = LR.build_all(cfg.pos, cfg.box, leaf_size=leaf_size, qbits=qbits)
     r2 = oracle.rlist2_table(cfg.rcut, cfg.skin)
     perm = b["perm"].astype(np.int64)
     rows = _alg1_rows(b["records"], b["ropes"], b["meta"], cfg.box, r2, np.zeros(cfg.n, np.int64),
@@ -260,7 +286,7 @@ def test_layout_two_types_and_empty_type():
     pos, box = W.uniform(300, [9.0, 9.0, 9.0], seed=13)
     types = (np.arange(300) % 4 == 0).astype(np.int32) * 2  # types 0 and 2, type 1 empty
     rcut = np.array([[1.2, 0.0, 1.6], [0.0, 1.0, 0.0], [1.6, 0.0, 2.0]], np.float32)
-    b = T.build_all(pos, box, types=types, ntypes=3, leaf_size=2)
+    b = LR.build_all(pos, box, types=types, ntypes=3, leaf_size=2)
     assert b["meta"][1]["count"] == 0
     r2 = oracle.rlist2_table(rcut, 0.25)
     perm = b["perm"].astype(np.int64)
@@ -274,7 +300,7 @@ def test_layout_two_types_and_empty_type():
 
 def test_layout_tree_smaller_than_a_leaf_run():
     pos = np.array([[1.0, 1.0, 1.0], [1.5, 1.0, 1.0], [6.0, 6.0, 6.0]], np.float32)
-    b = T.build_all(pos, np.full(3, 9.0, np.float32), leaf_size=4)
+    b = LR.build_all(pos, np.full(3, 9.0, np.float32), leaf_size=4)
     (m,) = b["meta"]
     assert b["records"].shape[0] == 0 and _run(m["root"]) == (0, 3)
 
@@ -282,7 +308,7 @@ def test_layout_tree_smaller_than_a_leaf_run():
 def test_layout_ropes_and_children():
     cfg = W.lj_fluid(500, seed=9)
     for leaf_size in (1, 2, 5, 16):
-        b = T.build_all(cfg.pos, cfg.box, leaf_size=leaf_size)
+        b = LR.build_all(cfg.pos, cfg.box, leaf_size=leaf_size)
         rec, ropes = b["records"], b["ropes"]
         (m,) = b["meta"]
         idx = np.arange(rec.shape[0])
