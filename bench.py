@@ -87,6 +87,80 @@ def traversal_bytes(n: int, nrecords: int, stored_pairs: int) -> int:
     return 16 * n + 36 * nrecords + 4 * stored_pairs + 4 * n
 
 
+def host_info() -> dict:
+    """CPU model and core counts of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo", encoding="utf-8") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    import oracle
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "oracle_threads": oracle.max_threads()}
+
+
+def gpu_rows(nbr, rows):
+    """Host copy of the GPU rows ``rows`` of the device list ``nbr``."""
+    import torch
+    idx = torch.as_tensor(np.asarray(rows, dtype=np.int64), device=nbr.device)
+    return nbr.index_select(0, idx).cpu().numpy()
+
+
+def row_parity(cfg, g_nbr_rows, g_cnt, max_nbr, queries, rp, cols):
+    """Compare GPU rows with the oracle's on ``queries`` (rows not overflowing):
+    entries in one row and not the other, split into band pairs (|d - r_list|
+    within 1e-5 r_list, where another rounding order may decide differently)
+    and mismatches (everything else)."""
+    import oracle
+    queries = np.asarray(queries)
+    c = g_cnt[queries].astype(np.int64)
+    ok = c <= max_nbr
+    big = np.iinfo(np.int64).max
+    col = np.arange(max_nbr)[None, :]
+    g = np.where(col < c[:, None], g_nbr_rows.astype(np.int64), big)
+    g.sort(axis=1)
+    ocnt = np.diff(rp)
+    exp = np.full((queries.size, max_nbr), big, dtype=np.int64)
+    r_of = np.repeat(np.arange(queries.size), ocnt)
+    within = np.arange(cols.size) - rp[r_of]
+    sel = within < max_nbr
+    exp[r_of[sel], within[sel]] = cols[sel]
+    differ = np.nonzero(ok & ((ocnt != c) | np.any(g != exp, axis=1)))[0]
+    L = np.asarray(cfg.box, dtype=np.float64)
+    pos = cfg.pos.astype(np.float64)
+    r2 = oracle.rlist2_table(cfg.rcut, cfg.skin)
+    t = np.zeros(cfg.n, np.int64) if cfg.types is None else cfg.types.astype(np.int64)
+    band = mism = 0
+    for k in differ:
+        i = int(queries[k])
+        got = g[k][g[k] != big]
+        for j in np.setxor1d(got, cols[rp[k]:rp[k + 1]]):
+            d = pos[j] - pos[i]
+            s = d / L
+            d = d - L * np.trunc(s + np.copysign(0.5, s))  # nearest image, halves away from zero
+            dist = np.sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2])
+            r = np.sqrt(max(r2[t[i], t[j]], 0.0))
+            if abs(dist - r) <= 1e-5 * r:
+                band += 1
+            else:
+                mism += 1
+    return {"rows_checked": int(np.count_nonzero(ok)), "band_pair_differences": band, "mismatches": mism}
+
+
+def band_report(cfg, queries=None, threads: int = 0) -> dict:
+    """Band pairs (directed) over the queried rows, both readings of the 1e-5 tolerance."""
+    import oracle
+    t0 = time.perf_counter()
+    a, b = oracle.band_counts(cfg.pos, cfg.box, cfg.rcut, cfg.skin, types=cfg.types, queries=queries,
+                              nthreads=threads)
+    return {"rows": int(cfg.n if queries is None else len(queries)), "rel_1e-5": int(a.sum()),
+            "abs_1e-5_sigma": int(b.sum()), "seconds": time.perf_counter() - t0}
+
+
 # HBM traffic of one k_traverse launch on lj8m with BENCH_OPTS, from two rocprofv3
 # counter passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) divided by the
 # factor the same counters read for a plain elementwise copy of known size (the
@@ -217,8 +291,10 @@ def f64_data(cfg, max_nbr: int, steps: int) -> dict:
 
 def grid_comparator(cfg, pos, max_nbr: int, steps: int) -> dict:
     """The same lists by the grid method the paper compares its tree with
-    (nlist_build_grid: cells at least as wide as the list radius, 27 cells per
-    particle, rows written entry by entry), timed over ``steps`` calls."""
+    (nlist_build_grid: cells at least as wide as the list radius, particles
+    sorted by cell, 27 cells per particle scanned by n cooperating lanes),
+    timed over ``steps`` calls for every n in 1..32; the fastest n is the
+    comparator (the paper reports the grid at its best n)."""
     import torch
     import paper_1901_08088_amd as Q
     n = cfg.n
@@ -226,19 +302,30 @@ def grid_comparator(cfg, pos, max_nbr: int, steps: int) -> dict:
     cnt = torch.empty(n, dtype=torch.int32, device="cuda")
     ovf = torch.empty(1, dtype=torch.int32, device="cuda")
     rc, skin = float(cfg.rcut[0, 0]), cfg.skin
-    g = Q.nlist_build_grid(pos, cfg.box, rc, skin, max_nbr, nbr, cnt, ovf)
-    for _ in range(2):
-        Q.nlist_build_grid(pos, cfg.box, rc, skin, max_nbr, nbr, cnt, ovf, grid=g)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    ev[0].record(stream)
-    for _ in range(steps):
-        Q.nlist_build_grid(pos, cfg.box, rc, skin, max_nbr, nbr, cnt, ovf, grid=g)
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    out = {"method": "uniform grid, cells >= r_list, 27-cell scan, one lane per particle in cell order",
-           "ms": ev[0].elapsed_time(ev[1]) / steps, "directed_pairs": int(cnt.sum())}
+    g = None
+    per = {}
+    pairs = None
+    for lanes in (1, 2, 4, 8, 16, 32):
+        for _ in range(2):
+            g = Q.nlist_build_grid(pos, cfg.box, rc, skin, max_nbr, nbr, cnt, ovf, grid=g, lanes=lanes)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(steps):
+            Q.nlist_build_grid(pos, cfg.box, rc, skin, max_nbr, nbr, cnt, ovf, grid=g, lanes=lanes)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        per[lanes] = ev[0].elapsed_time(ev[1]) / steps
+        p = int(cnt.sum())
+        if pairs is not None and p != pairs:
+            raise RuntimeError(f"grid pairs differ between lane counts: {p} != {pairs}")
+        pairs = p
+    best = min(per, key=per.get)
+    out = {"method": "uniform grid, cells >= r_list, particles sorted by cell, 27-cell scan by n cooperating "
+                     "lanes per particle (best n reported)",
+           "ms": per[best], "lanes": best, "ms_per_lanes": {str(k): v for k, v in per.items()},
+           "directed_pairs": pairs}
     g.free()
     del nbr
     torch.cuda.empty_cache()
@@ -334,6 +421,23 @@ def batched_vs_plain(steps: int) -> dict:
     if batch_pairs != plain_pairs:
         raise RuntimeError(f"batched pairs {batch_pairs} != plain pairs {plain_pairs}")
     log(f"batched: {batch_ms:.3f} ms per call")
+    # after timing: four replicas of the batched results (the smallest, the
+    # largest and two drawn at random) against the oracle -- every count and
+    # 500 sampled rows each
+    import oracle
+    rng = np.random.default_rng(3)
+    sizes = [c.n for c in cfgs]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), *rng.choice(len(cfgs), 2, replace=False).tolist()})
+    checked = {}
+    for k in picks:
+        c, y = cfgs[k], systems[k]
+        g_cnt = y["count"].cpu().numpy().astype(np.int64)
+        o_cnt = oracle.neighbor_counts(c.pos, c.box, c.rcut, c.skin)
+        q = np.sort(rng.choice(c.n, min(500, c.n), replace=False))
+        rp, cols = oracle.neighbor_lists(c.pos, c.box, c.rcut, c.skin, queries=q)
+        checked[c.name] = {"n": c.n, "count_mismatch_rows": int(np.count_nonzero(o_cnt != g_cnt)),
+                           **row_parity(c, gpu_rows(y["nbr"], q), g_cnt, 256, q, rp, cols)}
+    log(f"batched results checked: {checked}")
     for t in trees:
         Q.qbvh_free(t)
     Q.nlist_batch_release()
@@ -345,7 +449,7 @@ def batched_vs_plain(steps: int) -> dict:
             "batched_pairs_per_s": batch_pairs * 1e3 / batch_ms,
             "speedup": plain_ms / batch_ms, "plain_opts": BENCH_OPTS,
             "tuned": {k: st[k] for k in ("leaf_size", "qbits", "block_size", "candidates")},
-            "tuning_calls": calls}
+            "tuning_calls": calls, "results_checked_after_timing": checked}
 
 
 def served(seconds: float, load: float = 0.7) -> dict:
@@ -422,8 +526,25 @@ def served(seconds: float, load: float = 0.7) -> dict:
     srv = Q.Server(budget, max_inflight=2, max_batch=64)
     burst(srv, 1)
     st = poisson(srv, rate)
+    # after timing: the published results of four simulations (the smallest and
+    # largest slab and LJ fluid) against the oracle on the positions of their
+    # last request -- every count and 500 sampled rows each
+    import oracle
+    checked = {}
+    picks = {min((c for c in sims if kind in c.name), key=lambda c: c.n).meta["sim"] for kind in ("slab", "_lj_")}
+    picks |= {max((c for c in sims if kind in c.name), key=lambda c: c.n).meta["sim"] for kind in ("slab", "_lj_")}
+    for k in sorted(picks):
+        c = sims[k]
+        moved = W.Config(pos=cur[k].cpu().numpy(), box=c.box, rcut=c.rcut, skin=c.skin, name=c.name)
+        g_nbr, g_cnt, g_ovf = srv.read(k)
+        o_cnt = oracle.neighbor_counts(moved.pos, moved.box, moved.rcut, moved.skin)
+        q = np.sort(np.random.default_rng(k).choice(c.n, min(500, c.n), replace=False))
+        rp, cols = oracle.neighbor_lists(moved.pos, moved.box, moved.rcut, moved.skin, queries=q)
+        r = row_parity(moved, g_nbr[q], g_cnt.astype(np.int64), 256, q, rp, cols)
+        checked[c.name] = {"n": c.n, "count_mismatch_rows": int(np.count_nonzero(o_cnt != g_cnt)),
+                           "overflow": g_ovf, **r}
     srv.close()
-    log(f"continuous batching: {st}")
+    log(f"continuous batching: {st}; results checked: {checked}")
     fifo = Q.Server(budget, max_inflight=1, max_batch=1)
     burst(fifo, 1)
     fsat = burst(fifo, 1)
@@ -433,27 +554,113 @@ def served(seconds: float, load: float = 0.7) -> dict:
     keys = ("p50_ms", "p99_ms", "mean_ms", "requests_per_s", "particles_per_s", "mean_batch", "completed")
     out.update({"saturated_requests_per_s": sat, "arrival_rate_per_s": rate,
                 "continuous_batching": {k: st[k] for k in keys},
+                "results_checked_after_timing": checked,
                 "fifo_saturated_requests_per_s": fsat,
                 "fifo_one_at_a_time": {k: fst[k] for k in keys}})
     return out
 
 
-def cpu_baseline(cfg, sample_rows: int) -> dict:
-    """The oracle's cell list timed on this host for a bounded sample of rows."""
+def config_leg(name: str, steps: int, warmup: int, opts: dict, threads: int) -> dict:
+    """One configuration timed like the main leg (build and traversal with
+    events over ``steps`` steps after ``warmup``), then checked and timed
+    against the oracle on the host: every count, the rows of up to 2000
+    particles (all rows for small systems), band pairs of every row, and the
+    oracle's own time (cell list on all ``threads`` host threads; for
+    N <= 50000 also brute force on one thread and on all threads).  A
+    one-type configuration is also timed with the grid comparator."""
+    import torch
+    import oracle
+    import paper_1901_08088_amd as Q
+    wl = WORKLOADS[name]
+    cfg = make_config(wl)
+    n, max_nbr = cfg.n, wl["max_nbr"]
+    pos = torch.from_numpy(cfg.pos).cuda()
+    types = None if cfg.types is None else torch.from_numpy(cfg.types).cuda()
+    nbr = torch.empty((n, max_nbr), dtype=torch.int32, device="cuda")
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    ovf = torch.empty(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    tree = Q.qbvh_build(pos, types, cfg.box, cfg.ntypes, opts)
+    for _ in range(warmup):
+        Q.qbvh_build(pos, types, cfg.box, cfg.ntypes, opts, tree=tree)
+        Q.nlist_build(tree, cfg.rcut, cfg.skin, max_nbr, nbr, cnt, ovf)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in ev:
+        e[0].record(stream)
+        Q.qbvh_build(pos, types, cfg.box, cfg.ntypes, opts, tree=tree)
+        e[1].record(stream)
+        Q.nlist_build(tree, cfg.rcut, cfg.skin, max_nbr, nbr, cnt, ovf)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    build_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    trav_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    g_cnt = cnt.cpu().numpy().astype(np.int64)
+    pairs = int(g_cnt.sum())
+    info = Q.qbvh_info(tree)
+    tbytes = traversal_bytes(n, info["nrecords"], int(np.minimum(g_cnt, max_nbr).sum()))
+    out = {"workload": describe(wl, cfg), "n": n, "opts": opts, "steps": steps, "build_ms": build_ms,
+           "traverse_ms": trav_ms, "ms_per_step": wall * 1e3 / steps, "builds_per_s": steps / wall,
+           "directed_pairs": pairs, "pairs_per_s": pairs * steps / wall, "overflow": int(ovf.item()),
+           "traversal_algorithmic_gbs": tbytes / (trav_ms * 1e-3) / 1e9,
+           "traversal_hbm_frac": tbytes / (trav_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    # the oracle: counts of every row (timed), rows of a sample, band pairs
+    t0 = time.perf_counter()
+    o_cnt = oracle.neighbor_counts(cfg.pos, cfg.box, cfg.rcut, cfg.skin, types=cfg.types, method="cells",
+                                   nthreads=threads)
+    out["oracle_cells_all_threads_s"] = time.perf_counter() - t0
+    out["count_mismatch_rows"] = int(np.count_nonzero(o_cnt != g_cnt))
+    if n <= 50_000:
+        # (the thread count is passed on every call: a call sets the pool size)
+        for label, nt in (("oracle_brute_1_thread_s", 1), ("oracle_brute_all_threads_s", threads)):
+            t0 = time.perf_counter()
+            oracle.neighbor_counts(cfg.pos, cfg.box, cfg.rcut, cfg.skin, types=cfg.types, method="brute",
+                                   nthreads=nt)
+            out[label] = time.perf_counter() - t0
+    rng = np.random.default_rng(23)
+    q = np.arange(n) if n <= 50_000 else np.sort(rng.choice(n, 2000, replace=False))
+    rp, cols = oracle.neighbor_lists(cfg.pos, cfg.box, cfg.rcut, cfg.skin, types=cfg.types, queries=q,
+                                     method="cells", nthreads=threads)
+    out["rows"] = row_parity(cfg, gpu_rows(nbr, q), g_cnt, max_nbr, q, rp, cols)
+    out["band_pairs"] = band_report(cfg, threads=threads)
+    if cfg.types is None:
+        out["grid_comparator"] = grid_comparator(cfg, pos, max_nbr, 5)
+        out["tree_speedup"] = out["grid_comparator"]["ms"] / out["ms_per_step"]
+    log(f"{name}: {out}")
+    Q.qbvh_free(tree)
+    del nbr
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(cfg, sample_rows: int, threads: int):
+    """The oracle's cell list timed on this host: three runs, each over the
+    rows of a different random sample of ``sample_rows // 3`` particles (the
+    binning of all particles included), the median scaled linearly to all
+    rows.  Returns the report and the rows of the first sample."""
     import oracle
     n = cfg.n
-    rng = np.random.default_rng(7)
-    q = np.sort(rng.choice(n, min(sample_rows, n), replace=False)) if sample_rows < n else None
-    nq = n if q is None else q.size
-    t0 = time.perf_counter()
-    rp, _ = oracle.neighbor_lists(cfg.pos, cfg.box, cfg.rcut, cfg.skin, types=cfg.types, queries=q,
-                                  method="cells")
-    dt = time.perf_counter() - t0
-    full = dt * n / nq
-    return {"value": 1.0 / full, "unit": "nlist builds/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": (f"fp64 cell-list oracle, rows of {nq:,} of {n:,} particles (binning of all "
-                       f"{n:,} included), {dt:.2f} s wall, scaled linearly to all rows"),
-            "pairs_per_s": float(rp[-1]) / dt}
+    per = max(1, min(sample_rows // 3, n))
+    times, first = [], None
+    for rep in range(3):
+        rng = np.random.default_rng(7 + rep)
+        q = np.sort(rng.choice(n, per, replace=False)) if per < n else np.arange(n)
+        t0 = time.perf_counter()
+        rp, cols = oracle.neighbor_lists(cfg.pos, cfg.box, cfg.rcut, cfg.skin, types=cfg.types, queries=q,
+                                         method="cells", nthreads=threads)
+        times.append(time.perf_counter() - t0)
+        if first is None:
+            first = (q, rp, cols)
+    dt = float(np.median(times))
+    full = dt * n / per
+    rep = {"value": 1.0 / full, "unit": "nlist builds/s", "cores": threads, "kind": "oracle",
+           "sample": (f"fp64 cell-list oracle on {threads} host threads, median of 3 runs, each over the rows "
+                      f"of {per:,} random particles of {n:,} (binning of all {n:,} included; "
+                      f"{', '.join(f'{x:.2f}' for x in times)} s), scaled linearly to all rows"),
+           "pairs_per_s": float(first[1][-1]) / times[0]}
+    return rep, first
 
 
 def main(argv=None) -> int:
@@ -465,6 +672,10 @@ def main(argv=None) -> int:
     ap.add_argument("--leaf-size", type=int, default=BENCH_OPTS["leaf_size"])
     ap.add_argument("--qbits", type=int, default=BENCH_OPTS["qbits"])
     ap.add_argument("--block-size", type=int, default=BENCH_OPTS["block_size"])
+    ap.add_argument("--queries-per-wave", type=int, default=0,
+                    help="queries sharing one wavefront's walk (0 = chosen from the system size)")
+    ap.add_argument("--collapse-radius", type=float, default=0.0,
+                    help="subtree collapse by the cost model for this list radius (0 = runs of leaf size)")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="oracle rows timed for the CPU baseline (0 = skip)")
     ap.add_argument("--paper-steps", type=int, default=10,
@@ -479,6 +690,10 @@ def main(argv=None) -> int:
                     help="passes timed for the batched-vs-plain ensemble comparison (0 = skip)")
     ap.add_argument("--served-seconds", type=float, default=5.0,
                     help="Poisson-arrival time of the served-stream comparison (0 = skip)")
+    ap.add_argument("--config-steps", type=int, default=20,
+                    help="steps timed for each of the other configurations (LJ 4000, LJ 1M, colloid 1M, "
+                         "WCA 1M, spinodal 1M), each checked against the oracle and, for one type, timed "
+                         "against the grid comparator (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run a plain copy kernel of this size (counter calibration)")
     args = ap.parse_args(argv)
@@ -493,11 +708,18 @@ def main(argv=None) -> int:
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
 
+    host = host_info()  # before any oracle call: the thread count of the host's pool
+    threads = host["oracle_threads"]
+    log(f"host: {host}")
     wl = WORKLOADS[args.workload]
     log(f"generating {args.workload}")
     cfg = make_config(wl)
     n, max_nbr = cfg.n, wl["max_nbr"]
     opts = {"leaf_size": args.leaf_size, "qbits": args.qbits, "block_size": args.block_size}
+    if args.queries_per_wave:
+        opts["queries_per_wave"] = args.queries_per_wave
+    if args.collapse_radius > 0:
+        opts["collapse_radius"] = args.collapse_radius
 
     pos = torch.from_numpy(cfg.pos).cuda()
     types = None if cfg.types is None else torch.from_numpy(cfg.types).cuda()
@@ -547,6 +769,16 @@ def main(argv=None) -> int:
     if args.copy_probe_mib > 0:
         copy_probe(args.copy_probe_mib)
 
+    base = parity = None
+    if args.cpu_sample > 0:
+        log("cpu baseline (oracle) and row parity on its first sample")
+        base, (q, rp, cols) = cpu_baseline(cfg, args.cpu_sample, threads)
+        parity = {"count_mismatch_rows_in_sample": int(np.count_nonzero(np.diff(rp) != counts[q]))}
+        parity.update(row_parity(cfg, gpu_rows(nbr, q), counts, max_nbr, q, rp, cols))
+        parity["band_pairs_in_sample"] = band_report(cfg, queries=q, threads=threads)
+        del rp, cols
+        log(f"parity: {parity}")
+
     paper = None
     if args.paper_steps > 0 and cfg.types is None:
         log("paper-mode lists (10-bit grid)")
@@ -583,10 +815,14 @@ def main(argv=None) -> int:
         torch.cuda.empty_cache()
         serve = served(args.served_seconds)
 
-    base = None
-    if args.cpu_sample > 0:
-        log("cpu baseline (oracle)")
-        base = cpu_baseline(cfg, args.cpu_sample)
+    configs = None
+    if args.config_steps > 0:
+        configs = {}
+        for name in ("lj4000", "lj1m", "colloid1m", "wca1m", "spinodal1m"):
+            if name == args.workload:
+                continue
+            log(f"configuration {name}")
+            configs[name] = config_leg(name, args.config_steps, max(3, args.warmup // 2), BENCH_OPTS, threads)
 
     out = {
         "metric": METRIC,
@@ -614,6 +850,9 @@ def main(argv=None) -> int:
                                    else None),
                      "algorithmic_bytes": tbytes, "kernel_sources": kernel_source_hash()},
         "cpu_baseline": base,
+        "parity": parity,
+        "configs": configs,
+        "host": host,
         "paper_mode": paper,
         "single_graph": graph,
         "f64_data": f64,

@@ -10,7 +10,9 @@
  *     radix tree is emitted over the sorted codes and axis-aligned boxes are
  *     fit bottom-up, giving N - 1 internal nodes with two children each;
  *   - Section 2.2: node bounds are snapped outward to an integer grid over
- *     the root-node box and packed, with a skip rope, into 16-byte nodes;
+ *     the root-node box and packed with a skip rope (the paper's node is 16
+ *     bytes; this library stores both children of a node in one 32-byte
+ *     record, see QBVH_EXPORT_RECORDS);
  *   - Section 2.3 and Algorithm 1: every particle walks the tree without a
  *     stack (descend on overlap, follow the rope otherwise), once per
  *     periodic image whose search sphere touches the root box, testing a
@@ -87,6 +89,19 @@ typedef struct {
     int32_t validate;   /* 1: check every coordinate and type on the device and
                            wait for the result (the call then synchronizes the
                            stream); 0 (default): inputs are trusted */
+    float collapse_radius; /* subtree collapse (Section 2.3, last paragraph).  0 (default):
+                           every subtree of at most leaf_size particles is one leaf run.
+                           > 0: the tree is built with one particle per leaf and a subtree
+                           of at most leaf_size particles is collapsed into a run only when
+                           a cost estimate for search spheres of this radius (the expected
+                           list radius) says so: testing its particles (cost 1 each) must
+                           cost no more than testing its children's boxes (a record, cost
+                           4) plus the expected cost of the children, the chance that a
+                           sphere meets a box being taken proportional to the box's volume
+                           grown by the radius.  Must be finite and >= 0. */
+    int32_t queries_per_wave; /* queries that share one wavefront's walk: 1, 2, 4, 8, 16, 32
+                           or 64; 0 (default) chooses from the system size (64 for large
+                           systems, fewer for small ones) */
 } qbvh_opts_t;
 
 /*
@@ -162,14 +177,16 @@ QBVH_API int nlist_build(const qbvh_t *tree, const float *rcut, float skin, int3
 enum {
     QBVH_LIST_EXACT = 0, /* the exact list defined at the top (what nlist_build writes) */
     QBVH_LIST_PAPER = 1  /* the paper's lists (Section 2.3): j is listed for i when i's
-                            sphere (radius rcut[t_i][t_j] + skin, any periodic image)
+                            sphere (radius R = rcut[t_i][t_j] + skin, any periodic image)
                             overlaps j's cell box -- j's position snapped outward to the
-                            grid of its type's tree (Section 2.2), the leaf box of a
-                            one-particle leaf -- with no distance check.  A superset of
-                            the exact list; the extra entries are the paper's false
-                            positives (about rho (3 pi h R^2 + 6 h^2 R + h^3) per
-                            particle for bin width h).  The test uses the radius
-                            R/h (1 + 2^-20) + 0.02 in grid units, which covers its
+                            grid of its type's tree, the leaf box of a one-particle leaf --
+                            with no distance check.  The grid is the paper's (Section 2.2):
+                            the tree's root-node box split into 2^qbits - 1 bins along
+                            each axis, of width h_d = extent_d / (2^qbits - 1).  A superset
+                            of the exact list; the extra entries are the paper's false
+                            positives (about rho (hx hy hz + 2 R (hx hy + hy hz + hz hx)
+                            + pi R^2 (hx + hy + hz)) per particle).  The test uses the
+                            radius R (1 + 2^-20) + 0.02 max_d h_d, which covers its
                             rounding; the relation is not symmetric. */
 };
 
@@ -262,21 +279,37 @@ QBVH_API void nlist_batch_release(qbvh_stream_t stream);
  * arrive while others run are admitted as soon as a stream and memory free
  * up, and their work overlaps on the device.
  *
- * Sessions.  Every sim_id owns a session holding its list, counts and
- * overflow flag in device memory; they stay resident after the request
- * completes and are overwritten by the sim's next request.  (The tree is
- * rebuilt on every request, as the method rebuilds it at every list update,
- * so it lives only in the batch workspace.)  Requests of one sim run one at a
- * time, in submission order.
+ * Sessions.  Every sim_id owns a session holding result buffers (list,
+ * counts and overflow flag) in device memory.  The buffer of the sim's last
+ * completed request is its published result, resident until the sim's next
+ * request replaces it or the session is evicted.  (The tree is rebuilt on
+ * every request, as the method rebuilds it at every list update, so it lives
+ * only in the batch workspace.)  Requests of one sim run one at a time, in
+ * submission order.
  *
- * Admission by footprint.  A request needs its session's buffers
- * (n * max_nbr * 4 + n * 4 + 4 bytes) plus its share of the batch
- * workspace (qbvh_workspace_bytes(n)).  A request is admitted when the bytes
- * of all resident sessions and of the in-flight batches, plus its own, fit in
- * `budget_bytes`; idle sessions are evicted, least recently used first, to
- * make room.  A request that could never fit is refused at submission with
- * QBVH_EAGAIN; otherwise it waits in FIFO order (a request that does not fit
- * yet does not block smaller ones behind it).
+ * Results are read under a lease: qbvh_server_result hands out the published
+ * buffer and leases it; a leased buffer is neither written nor freed until
+ * qbvh_server_release returns the lease.  A client may submit the sim's next
+ * request before releasing: it runs into another buffer.
+ *
+ * Admission by footprint.  A request needs one result buffer
+ * (n * max_nbr * 4 + n * 4 + 4 bytes, each part rounded up to 256) that no
+ * lease holds, plus its share of its stream's batch workspace (about
+ * qbvh_workspace_bytes of the batch's particles).  In order of preference it
+ * writes: a spare buffer of its session that is large enough; a new buffer,
+ * if one fits after freeing spare buffers; its published buffer, if no lease
+ * holds it (the sim has no published result while the request runs); a new
+ * buffer after evicting whole idle sessions that hold no lease, least
+ * recently used first (an evicted sim's result is gone: qbvh_server_result
+ * then returns QBVH_EINVAL).  It is admitted when the bytes of all result
+ * buffers and of every stream's workspace, with its own, fit in
+ * `budget_bytes`.  A request that could never fit is refused at submission
+ * with QBVH_EAGAIN; otherwise it waits in FIFO order (a request that does not
+ * fit yet does not block smaller ones behind it).  When nothing is running
+ * and no queued request fits even with the streams' workspaces released, the
+ * budget is held by leased buffers: those requests complete with
+ * QBVH_EAGAIN.  So every submitted request completes, with its results or
+ * with an error.
  */
 typedef struct qbvh_server qbvh_server_t;
 
@@ -321,23 +354,35 @@ QBVH_API int qbvh_server_create(qbvh_server_t **srv, const qbvh_server_opts_t *o
  * request can never fit the budget.  Never blocks on the device. */
 QBVH_API int qbvh_server_submit(qbvh_server_t *srv, const qbvh_request_t *req, int64_t *ticket);
 
-/* *done = 1 once the request's results are on the device (its stream has
- * passed them), else 0.  A failed request reports its error code. */
+/* *done = 1 once the request has finished (its results, if any, are on the
+ * device), else 0; a finished request's return is its status (QBVH_OK or the
+ * error it failed with).  QBVH_EINVAL for an unknown ticket.  A ticket is
+ * forgotten once poll or wait has reported it finished. */
 QBVH_API int qbvh_server_poll(qbvh_server_t *srv, int64_t ticket, int32_t *done);
 
-/* Block until the request completes; returns its status. */
+/* Block until the request finishes; returns its status (one waiter per ticket). */
 QBVH_API int qbvh_server_wait(qbvh_server_t *srv, int64_t ticket);
 
-/* Device buffers of a sim's session: d_nbr [n][max_nbr], d_count [n],
- * d_overflow [1], as nlist_build writes them, for its last completed
- * request.  Valid until that sim's next request completes or the session is
- * evicted.  QBVH_EINVAL for an unknown sim or one with nothing completed. */
+/* Lease the published result of a sim: d_nbr [n][max_nbr], d_count [n],
+ * d_overflow [1], as nlist_build writes them, for its last completed request
+ * (any output pointer may be NULL).  The buffers stay valid and unchanged
+ * until the lease is returned with qbvh_server_release(srv, sim_id, *d_nbr);
+ * every successful call takes one lease.  QBVH_EINVAL for an unknown sim, one
+ * with nothing completed, or one whose session was evicted. */
 QBVH_API int qbvh_server_result(qbvh_server_t *srv, int32_t sim_id, const int32_t **d_nbr, const int32_t **d_count,
                        const int32_t **d_overflow, int32_t *n, int32_t *max_nbr);
 
+/* Return one lease of a sim's result buffer, named by the d_nbr pointer that
+ * qbvh_server_result gave.  QBVH_EINVAL if no such lease is held.  Device
+ * work that reads the buffers must be ordered before the release by the
+ * caller (e.g. synchronize the stream that reads them). */
+QBVH_API int qbvh_server_release(qbvh_server_t *srv, int32_t sim_id, const int32_t *d_nbr);
+
 QBVH_API int qbvh_server_stats(qbvh_server_t *srv, qbvh_server_stats_t *stats);
 
-/* Finish every queued and running request, then free the server. */
+/* Finish every queued and running request (each completes or fails as
+ * described above), then free the server and every session; leases end.
+ * No other call on the server may run concurrently with it. */
 QBVH_API void qbvh_server_destroy(qbvh_server_t *srv);
 
 /* Release a handle (waits for its pending work).  NULL is ignored. */
@@ -398,27 +443,33 @@ QBVH_API int qbvh_export(const qbvh_t *tree, int32_t what, void *d_dst, size_t d
 
 /*
  * nlist_build_grid -- the same exact list (one particle type) by the grid
- * method the paper compares its tree with (Section 1 and Section 4: a uniform
- * grid of cells at least as wide as the list radius; each particle tests the
- * particles of the 27 cells around its own).  It exists to measure the tree
- * against a grid on the same GPU.
+ * method the paper compares its tree with (Section 1, Section 3 and
+ * Section 4: particles sorted into a uniform grid of cells at least as wide
+ * as the list radius; each particle tests the particles of the 27 cells
+ * around its own, with n cooperating lanes per particle).  It exists to
+ * measure the tree against a grid on the same GPU.
  *
  *   grid    in/out.  *grid == NULL: a new handle is allocated (release with
  *           qgrid_free); otherwise its device workspace is reused, and
  *           reallocated after waiting for its pending work when too small.
  *   d_pos, n, box   as qbvh_build (n >= 0; coordinates in [0, box[d])).
  *   rcut, skin      list radius rcut + skin (rcut > 0, skin >= 0).
+ *   lanes   lanes per particle n: 1, 2, 4, 8, 16 or 32 (0: 4).  The n lanes
+ *           take a cell's candidates n at a time and combine their accepted
+ *           ones within the group; the paper picks the fastest n per system.
  *   max_nbr, d_nbr, d_count, d_overflow   as nlist_build (rows hold original
- *           indices; their order, unspecified, is the same from run to run).
+ *           indices in the order the cells and candidates are scanned, the
+ *           same from run to run for a given lanes).
  *
  * Cells per axis: floor(L_d / r_list), at most 1024.  Returns QBVH_EGEOM when
- * 2 r_list >= min L_d and QBVH_ENOTSUP when an axis would hold fewer than 3
- * cells.  Asynchronous on the stream; d_pos must stay valid until the work is
- * done.  Inputs are trusted (no device validation).
+ * 2 r_list >= min L_d, QBVH_ENOTSUP when an axis would hold fewer than 3
+ * cells, QBVH_EINVAL for a lanes value not listed.  Asynchronous on the
+ * stream; d_pos must stay valid until the work is done.  Inputs are trusted
+ * (no device validation).
  */
 typedef struct qgrid qgrid_t;
 QBVH_API int nlist_build_grid(qgrid_t **grid, const float *d_pos, int32_t n, const float box[3], float rcut,
-                     float skin, int32_t max_nbr, int32_t *d_nbr, int32_t *d_count,
+                     float skin, int32_t lanes, int32_t max_nbr, int32_t *d_nbr, int32_t *d_count,
                      int32_t *d_overflow, qbvh_stream_t stream);
 QBVH_API void qgrid_free(qgrid_t *grid);
 

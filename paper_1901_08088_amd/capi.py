@@ -24,7 +24,7 @@ EXPORT = dict(keys=1, perm=2, sorted=3, left=4, right=5, range_f=6, range_l=7, p
 
 C_API = ("qbvh_build", "qbvh_build_f64", "nlist_build", "nlist_build_ex", "nlist_build_many", "nlist_batch_stats", "nlist_batch_release",
          "qbvh_server_create", "qbvh_server_submit", "qbvh_server_poll", "qbvh_server_wait",
-         "qbvh_server_result", "qbvh_server_stats", "qbvh_server_destroy",
+         "qbvh_server_result", "qbvh_server_release", "qbvh_server_stats", "qbvh_server_destroy",
          "qbvh_free", "qbvh_strerror", "qbvh_last_hip_error", "qbvh_workspace_bytes", "qbvh_info",
          "qbvh_export", "nlist_build_grid", "qgrid_free")
 
@@ -40,7 +40,8 @@ class QbvhError(RuntimeError):
 
 class QbvhOpts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("qbits", ctypes.c_int32),
-                ("block_size", ctypes.c_int32), ("validate", ctypes.c_int32)]
+                ("block_size", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("collapse_radius", ctypes.c_float), ("queries_per_wave", ctypes.c_int32)]
 
 
 class QbvhBatchOpts(ctypes.Structure):
@@ -110,7 +111,7 @@ def lib():
                                          ctypes.POINTER(QbvhOpts), P]
             L.qbvh_build_f64.restype = ctypes.c_int
             L.nlist_build_grid.argtypes = [ctypes.POINTER(P), P, I32, ctypes.POINTER(ctypes.c_float), ctypes.c_float,
-                                           ctypes.c_float, I32, P, P, P, P]
+                                           ctypes.c_float, I32, I32, P, P, P, P]
             L.nlist_build_grid.restype = ctypes.c_int
             L.qgrid_free.argtypes = [P]
             L.qgrid_free.restype = None
@@ -135,6 +136,8 @@ def lib():
             L.qbvh_server_result.argtypes = [P, I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                                              ctypes.POINTER(I32), ctypes.POINTER(I32)]
             L.qbvh_server_result.restype = ctypes.c_int
+            L.qbvh_server_release.argtypes = [P, I32, P]
+            L.qbvh_server_release.restype = ctypes.c_int
             L.qbvh_server_stats.argtypes = [P, ctypes.POINTER(QbvhServerStats)]
             L.qbvh_server_stats.restype = ctypes.c_int
             L.qbvh_server_destroy.argtypes = [P]
@@ -186,7 +189,7 @@ def _opts(opts) -> QbvhOpts | None:
         return opts
     o = QbvhOpts()
     for k, v in dict(opts).items():
-        setattr(o, k, int(v))
+        setattr(o, k, float(v) if k == "collapse_radius" else int(v))
     return o
 
 
@@ -370,8 +373,10 @@ class Server:
         self._keep.pop(ticket, None)
         _check(rc, "qbvh_server_wait")
 
-    def result(self, sim_id: int):
-        """(nbr [n, max_nbr], count [n], overflow [1]) device tensors viewing the session's buffers."""
+    def result(self, sim_id: int) -> "Lease":
+        """Lease the sim's published result: a ``Lease`` whose ``nbr`` [n, max_nbr],
+        ``count`` [n] and ``overflow`` [1] device tensors view the session's buffers
+        until ``release()`` (also called on leaving a ``with`` block)."""
         import torch
         P = ctypes.c_void_p
         a, b, c = P(None), P(None), P(None)
@@ -382,7 +387,15 @@ class Server:
         nbr = torch.as_tensor(_DeviceArray(a.value, (n.value, m.value)), device=dev)
         cnt = torch.as_tensor(_DeviceArray(b.value, (n.value,)), device=dev)
         ovf = torch.as_tensor(_DeviceArray(c.value, (1,)), device=dev)
-        return nbr, cnt, ovf
+        return Lease(self, int(sim_id), a.value, nbr, cnt, ovf)
+
+    def read(self, sim_id: int):
+        """Host copies (nbr, count, overflow) of the sim's published result (leased while copying)."""
+        import torch
+        with self.result(sim_id) as r:
+            out = (r.nbr.cpu().numpy(), r.count.cpu().numpy(), int(r.overflow.cpu().item()))
+            torch.cuda.synchronize()
+        return out
 
     def stats(self) -> dict:
         st = QbvhServerStats()
@@ -400,6 +413,29 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Lease:
+    """One lease on a served result (qbvh_server_result / qbvh_server_release)."""
+
+    def __init__(self, server: Server, sim_id: int, nbr_ptr: int, nbr, count, overflow):
+        self._server, self.sim_id, self._ptr = server, sim_id, nbr_ptr
+        self.nbr, self.count, self.overflow = nbr, count, overflow
+
+    def release(self) -> None:
+        """Return the lease; work that reads the tensors must be finished (or ordered) first."""
+        if self._ptr is not None and self._server._h is not None:
+            _check(lib().qbvh_server_release(self._server._h, self.sim_id, ctypes.c_void_p(self._ptr)),
+                   "qbvh_server_release")
+        self._ptr = None
+        self.nbr = self.count = self.overflow = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.release()
+        return False
 
 
 def qbvh_free(tree: Tree) -> None:
@@ -458,14 +494,15 @@ class Grid:
 
 
 def nlist_build_grid(pos, box, rcut: float, skin: float, max_nbr: int, nbr, count, overflow,
-                     grid: Grid | None = None, stream=None) -> Grid:
-    """Exact one-type neighbor lists by the grid method (the comparator of the tree)."""
+                     grid: Grid | None = None, stream=None, lanes: int = 0) -> Grid:
+    """Exact one-type neighbor lists by the grid method (the comparator of the tree),
+    ``lanes`` cooperating lanes per particle (1..32, a power of 2; 0 = 4)."""
     import torch
     g = grid if grid is not None else Grid()
     n = int(pos.shape[0])
     b = (ctypes.c_float * 3)(*[float(x) for x in np.asarray(box, dtype=np.float32).reshape(3)])
     rc = lib().nlist_build_grid(ctypes.byref(g.ptr), _dev_ptr(pos, torch.float32, "pos"), n, b, float(rcut),
-                                float(skin), int(max_nbr), _dev_ptr(nbr, torch.int32, "nbr", allow_none=True),
+                                float(skin), int(lanes), int(max_nbr), _dev_ptr(nbr, torch.int32, "nbr", allow_none=True),
                                 _dev_ptr(count, torch.int32, "count"), _dev_ptr(overflow, torch.int32, "overflow"),
                                 _stream(stream))
     _check(rc, "nlist_build_grid")

@@ -44,6 +44,8 @@ int resolve_opts(const qbvh_opts_t *in, qbvh_opts_t *out) {
     if (o.block_size == 0) o.block_size = 64;
     if (!qbi::leaf_ok(o.leaf_size) || !qbi::qbits_ok(o.qbits) || !qbi::block_ok(o.block_size)) return QBVH_EINVAL;
     if (o.validate != 0 && o.validate != 1) return QBVH_EINVAL;
+    if (!(isfinite(o.collapse_radius) && o.collapse_radius >= 0.0f && o.collapse_radius < 1e30f)) return QBVH_EINVAL;
+    if (!qbi::qpw_ok(o.queries_per_wave)) return QBVH_EINVAL;
     *out = o;
     return QBVH_OK;
 }
@@ -219,7 +221,7 @@ int qbvh_build(qbvh_t **tree, const float *d_pos, const int32_t *d_type, int32_t
     t->stream = s;
 
     hipError_t e = qbi::launch_build(t->ws, d_pos, ntypes > 1 ? d_type : nullptr, n, ntypes, box, o.leaf_size,
-                                      o.qbits, o.validate, s);
+                                      o.qbits, o.collapse_radius, o.validate, s);
     if (e != hipSuccess) return hip_fail(e);
     return o.validate ? check_valid(t->ws.err, s) : QBVH_OK;
 }
@@ -275,7 +277,7 @@ int qbvh_build_f64(qbvh_t **tree, const double *d_pos, const int32_t *d_type, in
                                       t->err64, s);
     if (e == hipSuccess)
         e = qbi::launch_build(t->ws, t->pos32, ntypes > 1 ? d_type : nullptr, n, ntypes, t->box, o.leaf_size,
-                              o.qbits, 0, s);
+                              o.qbits, o.collapse_radius, 0, s);
     if (e == hipSuccess) e = qbi::launch_gather64(t->ws, n, d_pos, t->sorted64, s);
     if (e != hipSuccess) return hip_fail(e);
     return o.validate ? check_valid(t->err64, s) : QBVH_OK;
@@ -307,12 +309,13 @@ int nlist_build_ex(const qbvh_t *tree, const float *rcut, float skin, int32_t ma
     a.n = tree->n;
     a.ntypes = tree->ntypes;
     a.max_nbr = max_nbr;
-    a.qpw = qbi::queries_per_wave(tree->n);
+    a.qpw = tree->opts.queries_per_wave ? tree->opts.queries_per_wave : qbi::queries_per_wave(tree->n);
+    a.qbits = tree->opts.qbits;
     const bool vec4 = max_nbr > 0 && (max_nbr % 4) == 0 && (((uintptr_t)d_nbr) & 15u) == 0;
     const bool paper = mode == QBVH_LIST_PAPER;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    if (paper) e = qbi::launch_qpoint(tree->ws, tree->n, tree->ntypes, tree->opts.qbits, s);
+    if (paper) e = qbi::launch_qpoint(tree->ws, tree->n, tree->ntypes, tree->opts.qbits, a.lmax, s);
     if (e == hipSuccess) e = qbi::launch_traverse(a, tree->opts.block_size, vec4, paper, tree->ws.qpoint, s);
     if (e != hipSuccess) return hip_fail(e);
     return QBVH_OK;

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(64) void k_b_meta(int32_t nsys, const SysBuild *__r
         lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
         hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
     }
-    meta[idx] = tree_meta(lo, hi, y.ext_floor, qbits, s, c, leaf_size, P);
+    meta[idx] = tree_meta(lo, hi, y.ext_floor, qbits, s, c, c <= leaf_size, P);
 }
 
 __global__ __launch_bounds__(kBuildThreads) void k_b_emit(const int32_t *__restrict__ blk_first, int32_t nsys,
@@ -182,7 +182,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_emit(const int32_t *__restr
     const int32_t f = rf[i], l = rl[i];
     if (l - f + 1 <= leaf_size) return;  // inside a particle run
     const TreeMeta &m = meta[it.sys * QBVH_MAX_TYPES + (key >> 30)];
-    emit_record(i, f, l, m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, qbits, records, ropes);
+    emit_record(i, f, l, m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, nullptr, qbits, records,
+                ropes);
 }
 
 }  // namespace
@@ -208,7 +209,7 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t s) {
                            w.leaf_parent, w.visit, w.kept);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = launch_fit(w, b.total, s);
+        e = launch_fit(w, b.total, Collapse{0.f, 0.f, 0.f, b.leaf_size}, s);
         if (e != hipSuccess) return e;
     }
     e = launch_exclusive_scan(w.kept, b.total + 1, b.scan_part, s);

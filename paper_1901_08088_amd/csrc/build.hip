@@ -180,6 +180,12 @@ constexpr int kFitThreads = 1024;
 // each frontier node) and its workgroups many; N = 8M takes three level launches.
 constexpr int kFitFanout = 32;
 constexpr int kFrontierCap = 160;
+// A chunk's frontier holds nodes whose parent's range crosses one of the
+// chunk's two borders; the nodes whose range crosses a border form one chain
+// of the tree (they nest), so each border contributes at most one node per
+// tree level.  Keys are 32 bits plus a 32-bit position, so a radix tree has
+// at most 64 levels of internal nodes: 2 * (64 + 1) entries at most.
+static_assert(kFrontierCap >= 2 * (64 + 1), "fit frontier bound");
 
 __device__ __forceinline__ void frontier_push(int32_t c, uint32_t *s_fcount, int32_t *s_front, int32_t *err) {
     const uint32_t slot = atomicAdd(s_fcount, 1u);
@@ -192,6 +198,7 @@ __device__ __forceinline__ void frontier_push(int32_t c, uint32_t *s_fcount, int
 // First level: the chunk's node links, its particles' positions, the visit
 // counters and the boxes all live in LDS (loaded with coalesced reads), so a
 // climb touches global memory only to read its leaf's parent.
+template <bool kCost>
 __global__ __launch_bounds__(kFitThreads) void k_fit_local(const float4 *__restrict__ sorted,
                                                            const int32_t *__restrict__ left,
                                                            const int32_t *__restrict__ right,
@@ -201,8 +208,9 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_local(const float4 *__restr
                                                            const int32_t *__restrict__ leaf_parent, int32_t n,
                                                            float4 *__restrict__ box_lo, float4 *__restrict__ box_hi,
                                                            int32_t *__restrict__ front, uint32_t *__restrict__ fcount,
-                                                           int32_t *err) {
+                                                           int32_t *err, Collapse col, float *__restrict__ cost) {
     __shared__ float s_box[6][kFitChunk];
+    __shared__ float s_cost[kCost ? kFitChunk : 1];
     __shared__ float s_pos[3][kFitChunk];
     __shared__ int32_t s_link[5][kFitChunk];  // left, right, range first, range last, parent
     __shared__ uint32_t s_visit[kFitChunk];
@@ -270,6 +278,17 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_local(const float4 *__restr
                 s_box[d][j] = lo[d];
                 s_box[3 + d][j] = hi[d];
             }
+            if (kCost) {
+                // children's costs: a particle, or an internal node of the chunk finished before
+                float fc[2];
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const int32_t ch = s_link[side][j];
+                    fc[side] = ch < 0 ? col.kVball : fabsf(s_cost[ch - c0]);
+                }
+                s_cost[j] = node_cost(col, s_link[3][j] - s_link[2][j] + 1, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2],
+                                      fc[0], fc[1]);
+            }
             c = p;
             p = s_link[4][j];
         }
@@ -279,6 +298,7 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_local(const float4 *__restr
         if (s_visit[i] == 2) {
             box_lo[c0 + i] = make_float4(s_box[0][i], s_box[1][i], s_box[2][i], 0.0f);
             box_hi[c0 + i] = make_float4(s_box[3][i], s_box[4][i], s_box[5][i], 0.0f);
+            if (kCost) cost[c0 + i] = s_cost[i];
         }
     }
     const uint32_t fc = min(s_fcount, (uint32_t)kFrontierCap);
@@ -288,6 +308,7 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_local(const float4 *__restr
 
 // One level above the first: chunks of `chunk` positions, starting from the
 // frontiers of the `fan` previous-level chunks each contains.
+template <bool kCost>
 __global__ __launch_bounds__(kFitThreads) void k_fit_level(const float4 *__restrict__ sorted,
                                                            const int32_t *__restrict__ left,
                                                            const int32_t *__restrict__ right,
@@ -299,7 +320,8 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_level(const float4 *__restr
                                                            const uint32_t *__restrict__ fcount_in, uint32_t *visit,
                                                            float4 *box_lo, float4 *box_hi,
                                                            int32_t *__restrict__ front_out,
-                                                           uint32_t *__restrict__ fcount_out, int32_t *err) {
+                                                           uint32_t *__restrict__ fcount_out, int32_t *err,
+                                                           Collapse col, float *cost) {
     __shared__ int32_t s_front[kFrontierCap];
     __shared__ uint32_t s_fcount;
     __shared__ uint32_t s_off[kFitFanout + 1];
@@ -352,8 +374,15 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_level(const float4 *__restr
             const float4 *pb_lo = c1i < 0 ? sorted + ~c1i : box_lo + c1i;
             const float4 *pb_hi = c1i < 0 ? sorted + ~c1i : box_hi + c1i;
             const float4 alo = *pa_lo, ahi = *pa_hi, blo = *pb_lo, bhi = *pb_hi;
-            box_lo[p] = make_float4(fminf(alo.x, blo.x), fminf(alo.y, blo.y), fminf(alo.z, blo.z), 0.0f);
-            box_hi[p] = make_float4(fmaxf(ahi.x, bhi.x), fmaxf(ahi.y, bhi.y), fmaxf(ahi.z, bhi.z), 0.0f);
+            const float4 nlo = make_float4(fminf(alo.x, blo.x), fminf(alo.y, blo.y), fminf(alo.z, blo.z), 0.0f);
+            const float4 nhi = make_float4(fmaxf(ahi.x, bhi.x), fmaxf(ahi.y, bhi.y), fmaxf(ahi.z, bhi.z), 0.0f);
+            box_lo[p] = nlo;
+            box_hi[p] = nhi;
+            if (kCost) {
+                const float fa = c0i < 0 ? col.kVball : fabsf(cost[c0i]);
+                const float fb = c1i < 0 ? col.kVball : fabsf(cost[c1i]);
+                cost[p] = node_cost(col, pl - pf + 1, nlo.x, nlo.y, nlo.z, nhi.x, nhi.y, nhi.z, fa, fb);
+            }
             c = p;
             p = pp;
         }
@@ -368,7 +397,8 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_level(const float4 *__restr
 __global__ void k_meta(int32_t n, int32_t ntypes, const uint32_t *__restrict__ type_count,
                        const float4 *__restrict__ sorted, const float4 *__restrict__ box_lo,
                        const float4 *__restrict__ box_hi, const uint32_t *__restrict__ P, int32_t qbits,
-                       int32_t leaf_size, double ext_floor, TreeMeta *__restrict__ meta) {
+                       int32_t leaf_size, const float *__restrict__ cost, double ext_floor,
+                       TreeMeta *__restrict__ meta) {
     const int t = threadIdx.x;
     if (t >= ntypes) return;
     int32_t s = 0;
@@ -385,7 +415,43 @@ __global__ void k_meta(int32_t n, int32_t ntypes, const uint32_t *__restrict__ t
         lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
         hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
     }
-    meta[t] = tree_meta(lo, hi, ext_floor, qbits, s, c, leaf_size, P);
+    // the root (internal node s) is a run when its subtree was collapsed
+    const bool root_run = cost ? (c < 2 || cost[s] < 0.0f) : c <= leaf_size;
+    meta[t] = tree_meta(lo, hi, ext_floor, qbits, s, c, root_run, P);
+}
+
+// With the cost model: which internal nodes keep a record.  A node keeps one
+// unless it or an ancestor became a run (only nodes of at most leaf_size
+// particles can); kept_flag[i] records it for the emit, and kept[f] counts the
+// kept nodes whose range starts at f (the layout's scan).
+__global__ __launch_bounds__(kBuildThreads) void k_kept_collapse(int32_t n, int32_t ntypes,
+                                                                 const uint32_t *__restrict__ keys,
+                                                                 const uint32_t *__restrict__ type_count,
+                                                                 const int32_t *__restrict__ rf,
+                                                                 const int32_t *__restrict__ rl,
+                                                                 const int32_t *__restrict__ parent,
+                                                                 const float *__restrict__ cost, int32_t leaf_size,
+                                                                 uint32_t *__restrict__ kept_flag,
+                                                                 uint32_t *__restrict__ kept) {
+    const int32_t i = blockIdx.x * kBuildThreads + threadIdx.x;
+    if (i >= n) return;
+    const Segment g = segment_of(keys[i], n, ntypes, type_count);
+    if (i >= g.e - 1) return;  // not an internal node id
+    const int32_t f = rf[i];
+    bool keep = !(cost[i] < 0.0f);
+    if (keep && rl[i] - f + 1 <= leaf_size) {
+        // ancestors of at most leaf_size particles (the only ones that can be runs)
+        int32_t u = parent[i];
+        for (int step = 0; step < kMaxDepth && u >= 0 && rl[u] - rf[u] + 1 <= leaf_size; ++step) {
+            if (cost[u] < 0.0f) {
+                keep = false;
+                break;
+            }
+            u = parent[u];
+        }
+    }
+    kept_flag[i] = keep ? 1u : 0u;
+    if (keep) atomicAdd(&kept[f], 1u);
 }
 
 // One record per kept internal node (Karras id i).
@@ -401,25 +467,28 @@ __global__ __launch_bounds__(kBuildThreads) void k_emit(int32_t n, int32_t ntype
                                                         const float4 *__restrict__ box_hi,
                                                         const uint32_t *__restrict__ P,
                                                         const TreeMeta *__restrict__ meta, int32_t leaf_size,
-                                                        int32_t qbits, uint4 *__restrict__ records,
-                                                        int32_t *__restrict__ ropes) {
+                                                        const uint32_t *__restrict__ kept_flag, int32_t qbits,
+                                                        uint4 *__restrict__ records, int32_t *__restrict__ ropes) {
     const int32_t i = blockIdx.x * kBuildThreads + threadIdx.x;
     if (i >= n) return;
     const uint32_t key = keys[i];
     const Segment g = segment_of(key, n, ntypes, type_count);
     if (i >= g.e - 1) return;  // not an internal node id
     const int32_t f = rf[i], l = rl[i];
-    if (l - f + 1 <= leaf_size) return;  // inside a particle run
+    if (kept_flag ? kept_flag[i] == 0u : l - f + 1 <= leaf_size) return;  // inside a particle run
     const TreeMeta &m = meta[ntypes == 1 ? 0 : (key >> 30)];
-    emit_record(i, f, l, m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, qbits, records, ropes);
+    emit_record(i, f, l, m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, kept_flag, qbits,
+                records, ropes);
 }
 
 // Cell box of every sorted particle in its type tree's grid (the leaf box of a
 // one-particle leaf, Section 2.2), packed like a record box, plus its original
-// index: what paper-mode lists test (Section 2.3).
+// index: what paper-mode lists test (Section 2.3).  The grid is the paper's:
+// the root-node box split into 2^b - 1 bins along each axis, h_d =
+// max(extent_d, ext_floor) / (2^b - 1).
 __global__ __launch_bounds__(kBuildThreads) void k_qpoint(int32_t n, int32_t ntypes, const float4 *__restrict__ sorted,
                                                           const TreeMeta *__restrict__ meta, int32_t qbits,
-                                                          uint4 *__restrict__ qpoint) {
+                                                          double ext_floor, uint4 *__restrict__ qpoint) {
     const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
     if (k >= n) return;
     int t = 0;
@@ -427,9 +496,12 @@ __global__ __launch_bounds__(kBuildThreads) void k_qpoint(int32_t n, int32_t nty
         if (k >= meta[u].start && meta[u].count > 0) t = u;
     const TreeMeta &m = meta[t];
     const uint32_t qmax = (1u << qbits) - 1u;
+    double h[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) h[d] = axis_spacing(m.lo[d], m.hi[d], ext_floor, qbits);
     const float4 p = sorted[k];
-    qpoint[k] = make_uint4(quantize_axis(p.x, p.x, m.lo[0], m.h, qmax), quantize_axis(p.y, p.y, m.lo[1], m.h, qmax),
-                           quantize_axis(p.z, p.z, m.lo[2], m.h, qmax), (uint32_t)~__float_as_int(p.w));
+    qpoint[k] = make_uint4(quantize_axis(p.x, p.x, m.lo[0], h[0], qmax), quantize_axis(p.y, p.y, m.lo[1], h[1], qmax),
+                           quantize_axis(p.z, p.z, m.lo[2], h[2], qmax), (uint32_t)~__float_as_int(p.w));
 }
 
 inline dim3 grid_for(int64_t items) { return dim3((unsigned)((items + kBuildThreads - 1) / kBuildThreads)); }
@@ -453,28 +525,41 @@ hipError_t launch_gather64(const Workspace &w, int32_t n, const double *pos64, d
     return hipGetLastError();
 }
 
-hipError_t launch_fit(const Workspace &w, int32_t n, hipStream_t s) {
+namespace {
+
+template <bool kCost>
+void launch_fit_t(const Workspace &w, int32_t n, const Collapse &col, hipStream_t s) {
     int32_t nchunks = fit_chunks0(n);
-    hipLaunchKernelGGL(k_fit_local, dim3(nchunks), dim3(kFitThreads), 0, s, w.sorted, w.left, w.right, w.rf, w.rl,
-                       w.parent, w.leaf_parent, n, w.box_lo, w.box_hi, w.front[0], w.fcount[0], w.err);
+    hipLaunchKernelGGL(k_fit_local<kCost>, dim3(nchunks), dim3(kFitThreads), 0, s, w.sorted, w.left, w.right, w.rf,
+                       w.rl, w.parent, w.leaf_parent, n, w.box_lo, w.box_hi, w.front[0], w.fcount[0], w.err, col,
+                       w.cost);
     int64_t chunk = kFitChunk;
     int which = 0;
     while (chunk < n) {
         const int32_t nprev = nchunks;
         chunk *= kFitFanout;
         nchunks = (int32_t)((n + chunk - 1) / chunk);
-        hipLaunchKernelGGL(k_fit_level, dim3(nchunks), dim3(kFitThreads), 0, s, w.sorted, w.left, w.right, w.rf,
-                           w.rl, w.parent, w.leaf_parent, chunk, nprev, w.front[which], w.fcount[which], w.visit,
-                           w.box_lo, w.box_hi, w.front[which ^ 1], w.fcount[which ^ 1], w.err);
+        hipLaunchKernelGGL(k_fit_level<kCost>, dim3(nchunks), dim3(kFitThreads), 0, s, w.sorted, w.left, w.right,
+                           w.rf, w.rl, w.parent, w.leaf_parent, chunk, nprev, w.front[which], w.fcount[which],
+                           w.visit, w.box_lo, w.box_hi, w.front[which ^ 1], w.fcount[which ^ 1], w.err, col, w.cost);
         which ^= 1;
     }
+}
+
+}  // namespace
+
+hipError_t launch_fit(const Workspace &w, int32_t n, const Collapse &col, hipStream_t s) {
+    if (col.kVball > 0.0f)
+        launch_fit_t<true>(w, n, col, s);
+    else
+        launch_fit_t<false>(w, n, col, s);
     return hipGetLastError();
 }
 
-hipError_t launch_qpoint(const Workspace &w, int32_t n, int32_t ntypes, int32_t qbits, hipStream_t s) {
+hipError_t launch_qpoint(const Workspace &w, int32_t n, int32_t ntypes, int32_t qbits, double lmax, hipStream_t s) {
     if (n > 0)
         hipLaunchKernelGGL(k_qpoint, grid_for(n), dim3(kBuildThreads), 0, s, n, ntypes, w.sorted, w.meta, qbits,
-                           w.qpoint);
+                           lmax * 0x1p-24, w.qpoint);
     return hipGetLastError();
 }
 
@@ -488,7 +573,8 @@ size_t workspace_bytes(int32_t cap) {
     b += al(256 * tiles * 4) + al(256 * 4);   // histograms
     b += al((c + kSortedPad) * 16);           // sorted (+ padding read by whole-run loads)
     b += 6 * al(c * 4);                       // left right rf rl parent leaf_parent
-    b += al(c * 4);                           // visit
+    b += al(c * 4);                           // visit (fit counters, then kept flags)
+    b += al(c * 4);                           // cost (subtree collapse)
     b += 2 * al(c * 16);                      // boxes
     b += al((c + 1) * 4) + al(sb * 4);        // kept + scan partials
     b += al(c * 32) + al(c * 4);              // records + ropes
@@ -527,6 +613,7 @@ void workspace_carve(Workspace &w, void *base, int32_t cap) {
     w.parent = (int32_t *)take(c * 4);
     w.leaf_parent = (int32_t *)take(c * 4);
     w.visit = (uint32_t *)take(c * 4);
+    w.cost = (float *)take(c * 4);
     w.box_lo = (float4 *)take(c * 16);
     w.box_hi = (float4 *)take(c * 16);
     w.kept = (uint32_t *)take((c + 1) * 4);
@@ -545,8 +632,23 @@ void workspace_carve(Workspace &w, void *base, int32_t cap) {
     w.bytes = (size_t)(p - (char *)base);
 }
 
+Collapse collapse_model(float collapse_radius, int32_t leaf_size) {
+    Collapse c{0.0f, 0.0f, 0.0f, leaf_size};
+    if (collapse_radius > 0.0f) {
+        const double R = (double)collapse_radius;
+        const double pi = 3.141592653589793;
+        c.k2R = (float)(2.0 * R);
+        c.kPiR2 = (float)(pi * R * R);
+        c.kVball = (float)(4.0 / 3.0 * pi * R * R * R);
+    }
+    return c;
+}
+
 hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d_type, int32_t n, int32_t ntypes,
-                        const float box[3], int32_t leaf_size, int32_t qbits, int32_t validate, hipStream_t s) {
+                        const float box[3], int32_t leaf_size, int32_t qbits, float collapse_radius, int32_t validate,
+                        hipStream_t s) {
+    const Collapse col = collapse_model(collapse_radius, leaf_size);
+    const bool by_cost = col.kVball > 0.0f;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, w.type_count, w.err);
     const double sx = 1023.0 / (double)box[0];
     const double sy = 1023.0 / (double)box[1];
@@ -558,23 +660,28 @@ hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d
     if (ntypes > 1) hipLaunchKernelGGL(k_type_count, dim3(1), dim3(64), 0, s, w.keys, n, w.type_count);
     if (n > 0) {
         hipLaunchKernelGGL(k_gather, grid_for(n), dim3(kBuildThreads), 0, s, d_pos, w.vals, n, w.sorted);
+        // with the cost model, which nodes keep a record is known only after the fit
         hipLaunchKernelGGL(k_karras, grid_for(n), dim3(kBuildThreads), 0, s, w.keys, n, ntypes, w.type_count,
-                           leaf_size, w.left, w.right, w.rf, w.rl, w.parent, w.leaf_parent, w.visit, w.kept);
+                           by_cost ? INT32_MAX : leaf_size, w.left, w.right, w.rf, w.rl, w.parent, w.leaf_parent,
+                           w.visit, w.kept);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = launch_fit(w, n, s);
+        e = launch_fit(w, n, col, s);
         if (e != hipSuccess) return e;
+        if (by_cost)
+            hipLaunchKernelGGL(k_kept_collapse, grid_for(n), dim3(kBuildThreads), 0, s, n, ntypes, w.keys,
+                               w.type_count, w.rf, w.rl, w.parent, w.cost, leaf_size, w.visit, w.kept);
     }
     e = launch_exclusive_scan(w.kept, n + 1, w.scan_part, s);
     if (e != hipSuccess) return e;
     const double lmax = (double)fmaxf(box[0], fmaxf(box[1], box[2]));
     const double ext_floor = lmax * 0x1p-24;
     hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, s, n, ntypes, w.type_count, w.sorted, w.box_lo, w.box_hi,
-                       w.kept, qbits, leaf_size, ext_floor, w.meta);
+                       w.kept, qbits, leaf_size, by_cost ? w.cost : nullptr, ext_floor, w.meta);
     if (n > 0)
         hipLaunchKernelGGL(k_emit, grid_for(n), dim3(kBuildThreads), 0, s, n, ntypes, w.keys, w.type_count,
                            w.sorted, w.left, w.right, w.rf, w.rl, w.parent, w.box_lo, w.box_hi, w.kept, w.meta,
-                           leaf_size, qbits, w.records, w.ropes);
+                           leaf_size, by_cost ? w.visit : nullptr, qbits, w.records, w.ropes);
     return hipGetLastError();
 }
 

@@ -142,9 +142,54 @@ __device__ __forceinline__ uint32_t quantize_axis(float lo, float hi, float root
     return quantize_lo(lo, root, h, qmax) | (quantize_hi(hi, root, h, qmax) << 16);
 }
 
-// Tree description from the root box (exact fp32 min/max) of a segment.
+// Bin width along one axis of the paper's per-axis grid over a root box:
+// max(hi - lo, ext_floor) / (2^b - 1) in fp64.
+__host__ __device__ __forceinline__ double axis_spacing(float lo, float hi, double ext_floor, int32_t qbits) {
+    double e = (double)hi - (double)lo;
+    e = e > ext_floor ? e : ext_floor;
+    return e / (double)((1 << qbits) - 1);
+}
+
+// Subtree collapse by cost (Section 2.3, last paragraph: build with one
+// particle per leaf, then collapse subtrees by a heuristic).  For a search
+// sphere of radius R, the chance that it meets a box is taken proportional to
+// the volume of the box grown by R (Steiner's formula for an a x b x c box:
+// abc + 2R(ab + bc + ca) + pi R^2 (a + b + c) + 4/3 pi R^3).  A node of at
+// most leaf_size particles becomes a particle run when testing its particles
+// (cost 1 each) costs no more than testing its children's boxes (one record,
+// cost kRecordCost) plus the expected cost of the children; in volume-weighted
+// form, with F the cost times the grown volume:
+//   F(particle) = V(point)
+//   F(node)     = min(count V(node), kRecordCost V(node) + F(left) + F(right))
+// (the run when the first term is chosen).  fp32, in this order, with no
+// fused multiply-add.  Collapse constants: k2R = 2R, kPiR2 = pi R^2,
+// kVball = 4/3 pi R^3 (each computed in fp64, then rounded to fp32).
+constexpr float kRecordCost = 4.0f;
+
+struct Collapse {
+    float k2R, kPiR2, kVball;  // kVball == 0: no cost model (runs are the subtrees of at most leaf_size)
+    int32_t leaf_size;
+};
+
+__device__ __forceinline__ float grown_volume(const Collapse &c, float a, float b, float cz) {
+    const float ab = a * b, bc = b * cz, ca = cz * a;
+    return ((ab * cz + c.k2R * ((ab + bc) + ca)) + c.kPiR2 * ((a + b) + cz)) + c.kVball;
+}
+
+// F of a node of `count` particles with box lo/hi and children costs fl, fr;
+// negative when the node becomes a run.
+__device__ __forceinline__ float node_cost(const Collapse &c, int32_t count, float lx, float ly, float lz, float hx,
+                                           float hy, float hz, float fl, float fr) {
+    const float v = grown_volume(c, hx - lx, hy - ly, hz - lz);
+    const float leafc = (float)count * v;
+    const float split = kRecordCost * v + (fl + fr);
+    return (count <= c.leaf_size && leafc <= split) ? -leafc : split;
+}
+
+// Tree description from the root box (exact fp32 min/max) of a segment;
+// root_run: the whole tree is one particle run.
 __device__ __forceinline__ TreeMeta tree_meta(const float lo[3], const float hi[3], double ext_floor, int32_t qbits,
-                                              int32_t start, int32_t count, int32_t leaf_size,
+                                              int32_t start, int32_t count, bool root_run,
                                               const uint32_t *__restrict__ P) {
     TreeMeta m;
     double ext = 0.0;
@@ -159,21 +204,24 @@ __device__ __forceinline__ TreeMeta tree_meta(const float lo[3], const float hi[
     m.inv_h = 1.0 / m.h;
     m.start = start;
     m.count = count;
-    m.root = (count > leaf_size) ? (int32_t)P[start] : run_ref(start, count > 0 ? count : 1);
+    m.root = root_run ? run_ref(start, count > 0 ? count : 1) : (int32_t)P[start];
     m.end = (int32_t)P[start + count];
     m.pad[0] = m.pad[1] = 0;
     return m;
 }
 
-// Record of kept internal node i (particle range [f, l] longer than
-// leaf_size): both child boxes quantized against the tree's root box, both
-// child references, written at its preorder position, plus its rope.
+// Record of kept internal node i (a node with a record: particle range [f, l]
+// longer than leaf_size, or with the cost model, kept_flag[i] set): both
+// child boxes quantized against the tree's root box, both child references,
+// written at its preorder position, plus its rope.  A child is a record when
+// it is kept itself, otherwise a particle run.
 __device__ __forceinline__ void emit_record(int32_t i, int32_t f, int32_t l, const TreeMeta &m,
                                             const float4 *__restrict__ sorted, const int32_t *__restrict__ left,
                                             const int32_t *__restrict__ right, const int32_t *__restrict__ rf,
                                             const int32_t *__restrict__ rl, const int32_t *__restrict__ parent,
                                             const float4 *__restrict__ box_lo, const float4 *__restrict__ box_hi,
-                                            const uint32_t *__restrict__ P, int32_t leaf_size, int32_t qbits,
+                                            const uint32_t *__restrict__ P, int32_t leaf_size,
+                                            const uint32_t *__restrict__ kept_flag, int32_t qbits,
                                             uint4 *__restrict__ records, int32_t *__restrict__ ropes) {
     // Everything that does not depend on the preorder rank is loaded first,
     // so that those loads overlap the rank climb (a chain of dependent loads).
@@ -215,8 +263,9 @@ __device__ __forceinline__ void emit_record(int32_t i, int32_t f, int32_t l, con
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const int32_t count = cl[side] - cf[side] + 1;
+        const bool record = ch[side] >= 0 && (kept_flag ? kept_flag[ch[side]] != 0u : count > leaf_size);
         int32_t ref;
-        if (count > leaf_size)
+        if (record)
             ref = side == 0 ? at + 1 : (int32_t)right_rec;
         else
             ref = run_ref(cf[side], count);

@@ -6,10 +6,15 @@
 // candidate is decided by the same fp32 test with its error band and, inside
 // the band, by the fp64 arithmetic of the definition.
 //
-// Steps: cell index per particle; stable radix sort by cell (the sort of the
-// tree build); cell ranges from the sorted keys; then one lane per particle,
-// in cell order, looping over the particles of its 27 cells (periodic wrap
-// with the matching image shift).  Rows are written entry by entry.
+// Steps (Section 3): cell index per particle; stable radix sort by cell (the
+// sort of the tree build), so the particles of a cell are contiguous and in
+// index order; cell ranges from the sorted keys; then the traversal in the
+// sorted order with n lanes per particle (n a power of 2 below the wavefront
+// width): the n lanes of a particle take the candidates of each of its 27
+// cells in turn, n at a time (lane t the t-th of every n), and combine their
+// accepted candidates with a ballot over the group (the wave64 form of the
+// paper's warp shuffles), so the row is written n entries at a time in
+// candidate order.  n = 1 is one lane per particle.
 #include <math.h>
 #include <string.h>
 
@@ -82,14 +87,23 @@ __global__ __launch_bounds__(kGridThreads) void k_cell_ranges(const float *__res
     if (k == n - 1 || keys[k + 1] != key) end[key] = k + 1;
 }
 
+// The n = kN lanes of particle k (sorted position; lanes kN k .. kN k + kN - 1
+// of the launch, inside one wavefront).
+template <int kN>
 __global__ __launch_bounds__(kGridThreads) void k_grid_nlist(const float4 *__restrict__ sorted,
                                                              const uint32_t *__restrict__ keys, int32_t n,
                                                              GridGeom g, const int32_t *__restrict__ start,
                                                              const int32_t *__restrict__ end, double r2, float r2in,
                                                              float r2out, int32_t max_nbr, int32_t *__restrict__ nbr,
                                                              int32_t *__restrict__ count, int32_t *overflow) {
-    const int32_t k = blockIdx.x * kGridThreads + threadIdx.x;
-    if (k >= n) return;
+    const int64_t t = (int64_t)blockIdx.x * kGridThreads + threadIdx.x;
+    const int32_t k = (int32_t)(t / kN);
+    if (k >= n) return;  // the kN lanes of a group share k: a group leaves whole
+    const uint32_t lane = __lane_id();
+    const int32_t sub = (int32_t)(lane & (kN - 1));
+    // this group's lanes in the wavefront, and those below this lane
+    const uint64_t gmask = kN == 64 ? ~0ull : (((1ull << kN) - 1ull) << (lane & ~(uint32_t)(kN - 1)));
+    const uint64_t below = gmask & ((1ull << lane) - 1ull);
     const float4 q = sorted[k];
     const int32_t orig = ~__float_as_int(q.w);
     const uint32_t key = keys[k];
@@ -116,29 +130,39 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_nlist(const float4 *__res
                 const float qsx = (float)((double)q.x + sx), qsy = (float)((double)q.y + sy),
                             qsz = (float)((double)q.z + sz);
                 const int32_t c = (z * g.nc[1] + y) * g.nc[0] + x;
-                const int32_t j1 = end[c];
-                for (int32_t j = start[c]; j < j1; ++j) {
-                    if (j == k) continue;
-                    const float4 p = sorted[j];
-                    const float ax = p.x - qsx, ay = p.y - qsy, az = p.z - qsz;
-                    const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
-                    bool in = d2 <= r2in;
-                    if (!in && d2 <= r2out) {
-                        const double dx = ((double)p.x - (double)q.x) - sx;
-                        const double dy = ((double)p.y - (double)q.y) - sy;
-                        const double dz = ((double)p.z - (double)q.z) - sz;
-                        in = (dx * dx + dy * dy) + dz * dz <= r2;
+                const int32_t j0 = start[c], j1 = end[c];
+                // every lane of the group runs the same trips: the ballot sees the whole group
+                for (int32_t jb = j0; jb < j1; jb += kN) {
+                    const int32_t j = jb + sub;
+                    bool in = false;
+                    int32_t idx = 0;
+                    if (j < j1 && j != k) {
+                        const float4 p = sorted[j];
+                        idx = ~__float_as_int(p.w);
+                        const float ax = p.x - qsx, ay = p.y - qsy, az = p.z - qsz;
+                        const float d2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax));
+                        in = d2 <= r2in;
+                        if (!in && d2 <= r2out) {
+                            const double dx = ((double)p.x - (double)q.x) - sx;
+                            const double dy = ((double)p.y - (double)q.y) - sy;
+                            const double dz = ((double)p.z - (double)q.z) - sz;
+                            in = (dx * dx + dy * dy) + dz * dz <= r2;
+                        }
                     }
+                    const uint64_t acc = (uint64_t)__ballot(in) & gmask;
                     if (in) {
-                        if (cnt < max_nbr) row[cnt] = ~__float_as_int(p.w);
-                        ++cnt;
+                        const int32_t pos = cnt + (int32_t)__popcll(acc & below);
+                        if (pos < max_nbr) row[pos] = idx;
                     }
+                    cnt += (int32_t)__popcll(acc);
                 }
             }
         }
     }
-    count[orig] = cnt;
-    if (cnt > max_nbr) atomicOr(overflow, 1);
+    if (sub == 0) {
+        count[orig] = cnt;
+        if (cnt > max_nbr) atomicOr(overflow, 1);
+    }
 }
 
 __global__ void k_grid_clear_flag(int32_t *f) {
@@ -146,6 +170,27 @@ __global__ void k_grid_clear_flag(int32_t *f) {
 }
 
 inline dim3 blocks_for(int64_t items) { return dim3((unsigned)((items + kGridThreads - 1) / kGridThreads)); }
+
+template <int kN>
+void launch_grid_n(int32_t n, hipStream_t s, const float4 *sorted, const uint32_t *keys, const GridGeom &g,
+                   const int32_t *start, const int32_t *end, double r2, float r2in, float r2out, int32_t max_nbr,
+                   int32_t *nbr, int32_t *count, int32_t *overflow) {
+    hipLaunchKernelGGL(k_grid_nlist<kN>, blocks_for((int64_t)n * kN), dim3(kGridThreads), 0, s, sorted, keys, n, g,
+                       start, end, r2, r2in, r2out, max_nbr, nbr, count, overflow);
+}
+
+void launch_grid_nlist(int32_t lanes, int32_t n, hipStream_t s, const float4 *sorted, const uint32_t *keys,
+                       const GridGeom &g, const int32_t *start, const int32_t *end, double r2, float r2in,
+                       float r2out, int32_t max_nbr, int32_t *nbr, int32_t *count, int32_t *overflow) {
+    switch (lanes) {
+    case 1: launch_grid_n<1>(n, s, sorted, keys, g, start, end, r2, r2in, r2out, max_nbr, nbr, count, overflow); break;
+    case 2: launch_grid_n<2>(n, s, sorted, keys, g, start, end, r2, r2in, r2out, max_nbr, nbr, count, overflow); break;
+    case 4: launch_grid_n<4>(n, s, sorted, keys, g, start, end, r2, r2in, r2out, max_nbr, nbr, count, overflow); break;
+    case 8: launch_grid_n<8>(n, s, sorted, keys, g, start, end, r2, r2in, r2out, max_nbr, nbr, count, overflow); break;
+    case 16: launch_grid_n<16>(n, s, sorted, keys, g, start, end, r2, r2in, r2out, max_nbr, nbr, count, overflow); break;
+    default: launch_grid_n<32>(n, s, sorted, keys, g, start, end, r2, r2in, r2out, max_nbr, nbr, count, overflow); break;
+    }
+}
 
 }  // namespace
 }  // namespace qbi
@@ -161,8 +206,11 @@ void qgrid_free(qgrid_t *grid) {
 }
 
 int nlist_build_grid(qgrid_t **grid, const float *d_pos, int32_t n, const float box[3], float rcut, float skin,
-                     int32_t max_nbr, int32_t *d_nbr, int32_t *d_count, int32_t *d_overflow, qbvh_stream_t stream) {
+                     int32_t lanes, int32_t max_nbr, int32_t *d_nbr, int32_t *d_count, int32_t *d_overflow,
+                     qbvh_stream_t stream) {
     if (!grid || n < 0 || n > qbi::kMaxParticles || !qbi::box_ok(box) || max_nbr < 0 || !d_overflow) return QBVH_EINVAL;
+    if (lanes == 0) lanes = 4;
+    if (lanes < 1 || lanes > 32 || (lanes & (lanes - 1)) != 0) return QBVH_EINVAL;
     if (n > 0 && (!d_pos || !d_count || (max_nbr > 0 && !d_nbr))) return QBVH_EINVAL;
     if (!(isfinite(rcut) && rcut > 0.0f) || !(isfinite(skin) && skin >= 0.0f)) return QBVH_EINVAL;
     const double R = (double)rcut + (double)skin;
@@ -249,8 +297,8 @@ int nlist_build_grid(qgrid_t **grid, const float *d_pos, int32_t n, const float 
                            G->cell_end, ncells);
         hipLaunchKernelGGL(qbi::k_cell_ranges, qbi::blocks_for(n), dim3(qbi::kGridThreads), 0, s, d_pos, G->keys,
                            G->vals, n, G->sorted, G->cell_start, G->cell_end);
-        hipLaunchKernelGGL(qbi::k_grid_nlist, qbi::blocks_for(n), dim3(qbi::kGridThreads), 0, s, G->sorted, G->keys,
-                           n, g, G->cell_start, G->cell_end, r2, r2in, r2out, max_nbr, d_nbr, d_count, d_overflow);
+        qbi::launch_grid_nlist(lanes, n, s, G->sorted, G->keys, g, G->cell_start, G->cell_end, r2, r2in, r2out,
+                               max_nbr, d_nbr, d_count, d_overflow);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return qbi::hip_fail(e);

@@ -55,7 +55,8 @@ struct Workspace {
     float4 *sorted = nullptr;       // [cap + kSortedPad]
     int32_t *left = nullptr, *right = nullptr, *rf = nullptr, *rl = nullptr;
     int32_t *parent = nullptr, *leaf_parent = nullptr;
-    uint32_t *visit = nullptr;
+    uint32_t *visit = nullptr;      // fit visit counters; with the cost model, then kept flags
+    float *cost = nullptr;          // subtree collapse: volume-weighted cost per internal node (negative: a run)
     float4 *box_lo = nullptr, *box_hi = nullptr;
     uint32_t *kept = nullptr;       // [cap + 1]: kept-node counts, scanned in place
     uint32_t *scan_part = nullptr;  // [scan blocks + 1]
@@ -94,7 +95,7 @@ struct TravArgs {
     int32_t max_nbr;
     int32_t start;    // first sorted position of this system (0 for a single system)
     int32_t qpw;      // queries per wavefront (64, or 32/16/8 for small systems)
-    int32_t pad1;
+    int32_t qbits;    // grid bits of the tree (paper-mode cell boxes)
 };
 
 // One system of a batch as the build kernels see it.
@@ -156,6 +157,8 @@ inline bool leaf_ok(int32_t v) { return v >= 1 && v <= 16; }
 inline bool qbits_ok(int32_t v) { return v >= 8 && v <= 16; }
 // the traversal kernel is compiled for 64, 128, 192 and 256 work-items per group
 inline bool block_ok(int32_t v) { return v >= 64 && v <= 256 && (v % 64) == 0; }
+// queries per wavefront: 0 (automatic) or a power of 2 up to 64
+inline bool qpw_ok(int32_t v) { return v >= 0 && v <= 64 && (v & (v - 1)) == 0; }
 int hip_fail(hipError_t e);  // records the error for qbvh_last_hip_error, maps it to a code
 bool box_ok(const float box[3]);
 int list_radii(const float *rcut, float skin, int32_t ntypes, const float box[3],
@@ -166,9 +169,11 @@ void fill_trav_box(TravArgs &a, const float box[3]);
 void fill_trav_box(TravArgs &a, const double box[3]);
 
 // Launchers (all asynchronous on `s`; return the launch status).
+// collapse_radius > 0: subtrees of at most leaf_size particles become runs by
+// the cost model (build_common.h); 0: every subtree of at most leaf_size.
 hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d_type, int32_t n,
                         int32_t ntypes, const float box[3], int32_t leaf_size, int32_t qbits,
-                        int32_t validate, hipStream_t s);
+                        float collapse_radius, int32_t validate, hipStream_t s);
 hipError_t launch_traverse(const TravArgs &a, int32_t block, bool vec4, bool paper, const uint4 *qpoint,
                            hipStream_t s);
 // fp64 particle data: the positions rounded to fp32 for the build (with the
@@ -177,14 +182,16 @@ hipError_t launch_traverse(const TravArgs &a, int32_t block, bool vec4, bool pap
 hipError_t launch_to_f32(const double *pos64, const int32_t *type, int32_t n, int32_t ntypes, const double box[3],
                          int32_t validate, float *pos32, int32_t *err, hipStream_t s);
 hipError_t launch_gather64(const Workspace &w, int32_t n, const double *pos64, double *sorted64, hipStream_t s);
-hipError_t launch_qpoint(const Workspace &w, int32_t n, int32_t ntypes, int32_t qbits, hipStream_t s);
+// Paper-mode cell boxes; lmax is the largest periodic box edge (the extent floor is lmax 2^-24).
+hipError_t launch_qpoint(const Workspace &w, int32_t n, int32_t ntypes, int32_t qbits, double lmax, hipStream_t s);
 hipError_t launch_traverse_batch(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
                              uint32_t *hist, uint32_t *digit_total, int32_t n, int32_t tiles,
                              hipStream_t s);
 hipError_t launch_exclusive_scan(uint32_t *data, int32_t len, uint32_t *partials, hipStream_t s);
-hipError_t launch_fit(const Workspace &w, int32_t n, hipStream_t s);
+struct Collapse;
+hipError_t launch_fit(const Workspace &w, int32_t n, const Collapse &col, hipStream_t s);
 int32_t fit_chunks0(int32_t cap);
 // Stable sort of each segment [seg_off[s], seg_off[s+1]) of (keys, vals) on
 // its own; tile_first[s] = sum over earlier segments of seg_radix_tiles(size),

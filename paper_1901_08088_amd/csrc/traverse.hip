@@ -36,7 +36,7 @@
 // is near the cutoff.  Pairs with d32^2 <= ((R - eta)(1 - 2^-20))^2 are in,
 // pairs with d32^2 > ((R + eta)(1 + 2^-20))^2 are out, the rest (a shell a few
 // 1e-4 wide) take the fp64 path.
-#include "qbvh_internal.h"
+#include "build_common.h"
 
 namespace qbi {
 namespace {
@@ -100,8 +100,9 @@ struct Lane {
     int32_t k, orig;
     int32_t cnt;           // entries of the list so far
     int32_t flushed;       // entries already written to the row (a multiple of kFlush)
-    float px, py, pz;      // paper mode: query image in grid units (plain, not offset)
-    float rp2;             // paper mode: squared tight radius in grid units
+    float px, py, pz;      // paper mode: query image in per-axis grid units (plain, not offset)
+    float phx, phy, phz;   // paper mode: bin width of each axis
+    float rp2;             // paper mode: squared tight radius (world units)
 };
 
 template <bool kVec4, int kBlock>
@@ -241,8 +242,10 @@ __device__ __forceinline__ float cvt_hi(uint32_t w) {
 
 // Paper-mode pass (Section 2.3): a particle of the run is listed when the
 // lane's sphere overlaps the particle's own cell box (its leaf box in the
-// quantized tree), with no distance check.  The test runs in plain grid units
-// against the tight radius (R/h)(1 + 2^-20) + 0.02.
+// quantized tree, on the paper's per-axis grid), with no distance check.  The
+// nearest point is found in each axis's grid units and scaled to world units
+// by that axis's bin width; the test is against the tight radius
+// R (1 + 2^-20) + 0.02 max_d h_d.
 template <bool kSelf, int kBlock>
 __device__ __forceinline__ void run_paper(const uint4 *__restrict__ qrun, uint32_t count, uint32_t rel, bool hit,
                                           Lane &q, int32_t (*s_out)[kBlock]) {
@@ -254,9 +257,9 @@ __device__ __forceinline__ void run_paper(const uint4 *__restrict__ qrun, uint32
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         if ((uint32_t)u >= count) break;
-        const float cx = __builtin_amdgcn_fmed3f(q.px, cvt_lo(b[u].x), cvt_hi(b[u].x)) - q.px;
-        const float cy = __builtin_amdgcn_fmed3f(q.py, cvt_lo(b[u].y), cvt_hi(b[u].y)) - q.py;
-        const float cz = __builtin_amdgcn_fmed3f(q.pz, cvt_lo(b[u].z), cvt_hi(b[u].z)) - q.pz;
+        const float cx = (__builtin_amdgcn_fmed3f(q.px, cvt_lo(b[u].x), cvt_hi(b[u].x)) - q.px) * q.phx;
+        const float cy = (__builtin_amdgcn_fmed3f(q.py, cvt_lo(b[u].y), cvt_hi(b[u].y)) - q.py) * q.phy;
+        const float cz = (__builtin_amdgcn_fmed3f(q.pz, cvt_lo(b[u].z), cvt_hi(b[u].z)) - q.pz) * q.phz;
         const float d2 = __builtin_fmaf(cz, cz, __builtin_fmaf(cy, cy, cx * cx));
         const bool other = !kSelf || (uint32_t)u != rel;
         s_out[q.cnt & (kRing - 1)][threadIdx.x] = (int32_t)b[u].w;
@@ -496,7 +499,13 @@ __device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 
         for (int o = 32; o >= 1; o >>= 1) wave_bits |= (uint32_t)__shfl_xor((int)wave_bits, o, 64);
         wave_bits = (uint32_t)uniform((int32_t)wave_bits);
 
-        const double rg = R * m.inv_h;
+        // fp64 data: the tree and the query are the data rounded to fp32, which
+        // moves each point by up to 2^-24 L_max per axis, so a pair's distance
+        // by up to sqrt(3) 2^-23 L_max; the node test widens the sphere by that
+        // much before the two-bin pad (which alone covers it only when the
+        // tree's root box is not much smaller than the periodic box)
+        const double rshift = kF64 ? 1.7320508075688772 * 0x1p-23 * a.lmax : 0.0;
+        const double rg = (R + rshift) * m.inv_h;
         const double rgp = rg * (1.0 + 0x1p-20) + 2.0;
         const float r2g = lane_on ? (float)(rgp * rgp * (1.0 + 0x1p-20)) : -1.0f;
         // fp64 data adds the rounding of both points to fp32 (2^-24 L each per
@@ -507,10 +516,21 @@ __device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 
         q.r2in = (float)(rin * rin * (1.0 - 0x1p-20));
         q.r2out = (float)(rout * rout * (1.0 + 0x1p-20));
         const int32_t root = m.root, end = m.end;
+        double ph[3] = {1.0, 1.0, 1.0};
         if (kPaper) {
-            // covers the rounding of the query's grid position (at most
-            // 2^-24 of 65535 bins) and of the fp32 distance
-            const double rp = rg * (1.0 + 0x1p-20) + 0.02;
+            // the paper's per-axis bins (as the cell boxes were quantized); the
+            // pad covers the rounding of the query's grid position (at most
+            // 2^-24 of 65535 bins per axis) and of the fp32 distance
+            double hmax = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                ph[d] = axis_spacing(m.lo[d], m.hi[d], a.lmax * 0x1p-24, a.qbits);
+                hmax = ph[d] > hmax ? ph[d] : hmax;
+            }
+            q.phx = (float)ph[0];
+            q.phy = (float)ph[1];
+            q.phz = (float)ph[2];
+            const double rp = R * (1.0 + 0x1p-20) + 0.02 * hmax;
             q.rp2 = (float)(rp * rp * (1.0 + 0x1p-20));
         }
 
@@ -530,9 +550,9 @@ __device__ __forceinline__ void traverse_block(Args &a, int32_t li, const uint4 
             q.uy = (float)((((double)q.y + sy) - (double)m.lo[1]) * m.inv_h + 8388608.0);
             q.uz = (float)((((double)q.z + sz) - (double)m.lo[2]) * m.inv_h + 8388608.0);
             if (kPaper) {
-                q.px = (float)((((double)q.x + sx) - (double)m.lo[0]) * m.inv_h);
-                q.py = (float)((((double)q.y + sy) - (double)m.lo[1]) * m.inv_h);
-                q.pz = (float)((((double)q.z + sz) - (double)m.lo[2]) * m.inv_h);
+                q.px = (float)((((double)q.x + sx) - (double)m.lo[0]) / ph[0]);
+                q.py = (float)((((double)q.y + sy) - (double)m.lo[1]) / ph[1]);
+                q.pz = (float)((((double)q.z + sz) - (double)m.lo[2]) / ph[2]);
             }
             if (root < 0) {  // a tree of at most leaf_size particles is one run
                 take_run<kVec4, kBlock, kPaper, kF64>(root, on, __ballot(on), q, img, a.L, sorted, qpoint, sorted64,

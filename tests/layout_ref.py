@@ -25,6 +25,12 @@ Layout:
   The left child's record is the next record; ropes[v] is the record after
   v's subtree.  A tree of at most ``leaf_size`` particles has no record: its
   root is a run.
+- Subtree collapse by cost (``collapse_radius`` R > 0): a node of at most
+  ``leaf_size`` particles becomes a run when
+      count V(node) <= 4 V(node) + F(left) + F(right),
+  F(particle) = V(point), F(node) = the smaller side, with V the node box's
+  volume grown by R (Steiner's formula), all in fp32 in the library's order;
+  a node keeps a record unless it or an ancestor became a run.
 """
 from __future__ import annotations
 
@@ -38,12 +44,35 @@ def iso_spacing(lo, hi, box, qbits: int) -> float:
     return float(np.max(T.grid_spacing(lo, hi, box, qbits)))
 
 
+def collapse_flags(tree: dict, boxes: dict, leaf_size: int, collapse_radius: float) -> dict:
+    """{(f, l): True} for the internal nodes that become runs under the cost model."""
+    f32 = np.float32
+    R = float(np.float32(collapse_radius))
+    pi = 3.141592653589793
+    k2R, kPiR2, kVball = f32(2.0 * R), f32(pi * R * R), f32(4.0 / 3.0 * pi * R * R * R)
+    F, coll = {}, {}
+    for (f, l) in sorted(tree, key=lambda fl: fl[1] - fl[0]):  # children before parents
+        g = tree[(f, l)]
+        lo, hi = boxes[(f, l)]
+        a, b, c = f32(hi[0] - lo[0]), f32(hi[1] - lo[1]), f32(hi[2] - lo[2])
+        ab, bc, ca = f32(a * b), f32(b * c), f32(c * a)
+        v = f32(f32(f32(f32(ab * c) + f32(k2R * f32(f32(ab + bc) + ca))) + f32(kPiR2 * f32(f32(a + b) + c))) + kVball)
+        fc = [kVball if cf == cl else abs(F[(cf, cl)]) for (cf, cl) in ((f, g), (g + 1, l))]
+        count = l - f + 1
+        leafc = f32(f32(count) * v)
+        split = f32(f32(f32(4.0) * v) + f32(fc[0] + fc[1]))
+        coll[(f, l)] = bool(count <= leaf_size and leafc <= split)
+        F[(f, l)] = f32(-leafc) if coll[(f, l)] else split
+    return coll
+
+
 def run_ref(first: int, count: int) -> int:
     """Reference to the particle run [first, first + count) (negative int32)."""
     return ~((first << 4) | (count - 1))
 
 
-def record_layout(sorted_pos, sorted_keys, ntypes: int, box, leaf_size: int = 1, qbits: int = 16):
+def record_layout(sorted_pos, sorted_keys, ntypes: int, box, leaf_size: int = 1, qbits: int = 16,
+                  collapse_radius: float = 0.0):
     """Two-wide quantized records for all types' trees.
 
     Returns (records uint32 [M, 8], ropes int32 [M], meta list); ``meta[t]``
@@ -62,7 +91,12 @@ def record_layout(sorted_pos, sorted_keys, ntypes: int, box, leaf_size: int = 1,
         rlo = p[s:e].min(axis=0)
         rhi = p[s:e].max(axis=0)
         h = iso_spacing(rlo, rhi, box, qbits)
-        if e - s <= leaf_size:
+        if collapse_radius > 0:
+            coll = collapse_flags(tree, T.node_boxes(p, tree), leaf_size, collapse_radius)
+            is_run = lambda f, l: f == l or coll[(f, l)]  # noqa: E731
+        else:
+            is_run = lambda f, l: l - f + 1 <= leaf_size  # noqa: E731
+        if is_run(s, e - 1):
             meta.append(dict(start=s, count=e - s, root=run_ref(s, e - s), end=first, lo=rlo, hi=rhi, h=h))
             continue
 
@@ -78,7 +112,7 @@ def record_layout(sorted_pos, sorted_keys, ntypes: int, box, leaf_size: int = 1,
             records.append(child_box(*kids[0]) + child_box(*kids[1]) + [0, 0])
             ropes.append(-1)
             for side, (cf, cl) in enumerate(kids):
-                if cl - cf + 1 > leaf_size:
+                if not is_run(cf, cl):
                     ref = emit(cf, cl)
                 else:
                     ref = run_ref(cf, cl - cf + 1)
@@ -92,9 +126,11 @@ def record_layout(sorted_pos, sorted_keys, ntypes: int, box, leaf_size: int = 1,
     return arr, np.array(ropes, dtype=np.int32), meta
 
 
-def build_all(pos, box, types=None, ntypes: int = 1, leaf_size: int = 1, qbits: int = 16):
+def build_all(pos, box, types=None, ntypes: int = 1, leaf_size: int = 1, qbits: int = 16,
+              collapse_radius: float = 0.0):
     """The oracle's build steps plus the library's record layout."""
     b = T.build_steps(pos, box, types, ntypes)
-    records, ropes, meta = record_layout(b["sorted_pos"], b["sorted_keys"], ntypes, box, leaf_size, qbits)
+    records, ropes, meta = record_layout(b["sorted_pos"], b["sorted_keys"], ntypes, box, leaf_size, qbits,
+                                         collapse_radius)
     b.update(records=records, ropes=ropes, meta=meta)
     return b

@@ -76,6 +76,12 @@ def _build_rc(n=10, ntypes=1, box=(5.0, 5.0, 5.0), opts=None, pos=1, typ=None, t
     dict(opts={"block_size": 512}),
     dict(opts={"block_size": 1024}),
     dict(opts={"validate": 2}),
+    dict(opts={"collapse_radius": -1.0}),
+    dict(opts={"collapse_radius": float("nan")}),
+    dict(opts={"collapse_radius": float("inf")}),
+    dict(opts={"queries_per_wave": 3}),
+    dict(opts={"queries_per_wave": 128}),
+    dict(opts={"queries_per_wave": -4}),
 ])
 def test_build_rejects_bad_arguments_without_device_work(kwargs):
     assert _build_rc(**kwargs) == capi.EINVAL

@@ -4,6 +4,8 @@ path (identical counts), eager and graph-replayed, while tuning and after."""
 import numpy as np
 import pytest
 
+import oracle
+
 import paper_1901_08088_amd as Q
 import workloads as W
 
@@ -130,11 +132,13 @@ def test_batch_autotuner_freezes_and_stays_exact():
     _check_all(cfgs, batch_results(systems, cfgs), 256, _plain_counts(cfgs, 256))
 
 
+@pytest.mark.timeout(900)
 def test_batch_full_ensemble():
     """The 256-replica ensemble at full size (N log-uniform in [2000, 200000],
     density 0.3-0.9, rc 2.5-3.0, skin 0.4, max_nbr 256), graph-replayed after
-    tuning: every count equals the single-system path's, and sampled rows of
-    every replica equal the oracle's."""
+    tuning: every count of every replica equals the oracle's (and the
+    single-system path's), and sampled rows of every replica equal the
+    oracle's."""
     torch = require_gpu()
     cfgs = W.ensemble()
     total = sum(c.n for c in cfgs)
@@ -151,6 +155,11 @@ def test_batch_full_ensemble():
     plain = _plain_counts(cfgs, 256)
     for k, c in enumerate(cfgs):
         nbr, cnt, ovf = res[k]
+        ocnt = oracle.neighbor_counts(c.pos, c.box, c.rcut, c.skin, method="cells")
+        assert np.array_equal(cnt.astype(np.int64), ocnt), f"replica {k}: counts differ from the oracle"
+        if k % 32 == 31:
+            print(f"[batch] replicas 0..{k}: counts equal to the oracle's", flush=True)
+        assert ovf == int((ocnt > 256).any())
         assert np.array_equal(cnt, plain[k]), f"replica {k}: counts differ from the single-system path"
         q = rows[c.name]
         full = np.full((c.n, 256), -7, np.int32)

@@ -37,6 +37,17 @@ def test_f64_two_types_rows():
     compare_rows(cfg, nbr, cnt, ovf, 256)
 
 
+@pytest.mark.parametrize("opts", [None, {"leaf_size": 4}, {"leaf_size": 1, "qbits": 16}])
+def test_f64_compact_type_near_cutoff(opts):
+    # a type of 40 particles within 0.1 sigma in a box of edge 100: its tree's bins
+    # (0.1 / 65535) are far below the shift of a pair's distance when both points
+    # round to fp32 (up to sqrt(3) 2^-23 100); pairs at 2.5 (1 +- 1e-9..1e-6) from it
+    cfg = W.compact_type_f64()
+    _, nbr, cnt, ovf = run_nlist(cfg, 512, opts=opts)
+    assert ovf == 0
+    compare_rows(cfg, nbr, cnt, ovf, 512, method="brute")
+
+
 def test_f64_rebuild_between_precisions_reuses_the_handle():
     c32 = W.lj_fluid(4000)
     c64 = W.as_f64(c32, seed=4)

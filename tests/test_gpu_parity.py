@@ -21,11 +21,13 @@ from nlist_check import compare_rows, export, require_gpu, run_nlist, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _step_parity(cfg, leaf_size=1, qbits=16):
+def _step_parity(cfg, leaf_size=1, qbits=16, collapse_radius=0.0):
     torch = require_gpu()
     pos, types = to_dev(cfg)
-    tree = Q.qbvh_build(pos, types, cfg.box, cfg.ntypes, {"leaf_size": leaf_size, "qbits": qbits})
-    ref = LR.build_all(cfg.pos, cfg.box, types=cfg.types, ntypes=cfg.ntypes, leaf_size=leaf_size, qbits=qbits)
+    tree = Q.qbvh_build(pos, types, cfg.box, cfg.ntypes,
+                        {"leaf_size": leaf_size, "qbits": qbits, "collapse_radius": collapse_radius})
+    ref = LR.build_all(cfg.pos, cfg.box, types=cfg.types, ntypes=cfg.ntypes, leaf_size=leaf_size, qbits=qbits,
+                       collapse_radius=collapse_radius)
     n = cfg.n
     info = Q.qbvh_info(tree)
     keys = export(tree, "keys", n, torch.int32).view(np.uint32)
@@ -84,6 +86,21 @@ def test_build_steps_lj4000(leaf_size, qbits):
     _step_parity(W.lj_fluid(4000), leaf_size=leaf_size, qbits=qbits)
 
 
+@pytest.mark.parametrize("make,leaf_size,radius", [
+    (lambda: W.lj_fluid(4000), 16, 3.4), (lambda: W.lj_fluid(4000), 16, 1.0), (lambda: W.lj_fluid(4000), 8, 2.0),
+    (lambda: W.wca_fluid(9000, seed=5), 16, 1.52), (lambda: W.spinodal(12000, seed=6), 16, 3.4)])
+def test_build_steps_cost_collapse(make, leaf_size, radius):
+    # subtree collapse by the cost model: the same records as the layout helper
+    _step_parity(make(), leaf_size=leaf_size, collapse_radius=radius)
+
+
+def test_build_steps_cost_collapse_two_types():
+    pos, box = W.uniform(6000, [14.0, 14.0, 14.0], seed=22)
+    types = np.where(np.arange(6000) % 4 == 0, 1, 0).astype(np.int32)
+    _step_parity(W.Config(pos=pos, box=box, rcut=np.ones((2, 2), np.float32), skin=0.2, types=types),
+                 leaf_size=12, collapse_radius=1.2)
+
+
 def test_build_steps_duplicate_codes():
     # many coincident and near-coincident points: equal Morton codes, ties by position
     rng = np.random.default_rng(5)
@@ -113,7 +130,8 @@ def test_lj4000_exact_lists_and_determinism():
 
 @pytest.mark.parametrize("opts", [{"leaf_size": 1, "qbits": 10}, {"leaf_size": 4}, {"leaf_size": 8, "qbits": 12},
                                   {"leaf_size": 16}, {"leaf_size": 13, "qbits": 10, "block_size": 128},
-                                  {"block_size": 64}, {"block_size": 192, "leaf_size": 2}])
+                                  {"block_size": 64}, {"block_size": 192, "leaf_size": 2},
+                                  {"collapse_radius": 3.4}, {"collapse_radius": 0.7, "leaf_size": 9}])
 def test_lj4000_options(opts):
     cfg = W.lj_fluid(4000)
     _, nbr, cnt, ovf = run_nlist(cfg, 256, opts)

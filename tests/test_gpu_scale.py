@@ -47,3 +47,27 @@ def test_lj_fluid_full_size(n, kind):
         c = gcnt[i]
         assert sorted(rows[q, :c].tolist()) == cols[rp[q]:rp[q + 1]].tolist(), i
     print(f"[scale] {kind} N={n} pairs={int(gcnt.sum())} mean={gcnt.mean():.3f} ok", flush=True)
+
+
+@pytest.mark.parametrize("kind", ["lj", "colloid"])
+def test_raw_rows_are_deterministic_at_1m(kind):
+    # the same input built and listed twice: every raw row identical entry by
+    # entry (not only as a set), every count and the flag identical
+    torch = require_gpu()
+    cfg = W.lj_fluid(1_000_000) if kind == "lj" else W.colloid_solvent(1_000_000)
+    n = cfg.n
+    print(f"[scale] determinism {kind} N={n}", flush=True)
+    pos = torch.from_numpy(cfg.pos).cuda()
+    types = None if cfg.types is None else torch.from_numpy(cfg.types).cuda()
+    out = []
+    for rep in range(2):
+        tree = Q.qbvh_build(pos, types, cfg.box, cfg.ntypes, BENCH_OPTS)
+        nbr = torch.full((n, 256), -7, dtype=torch.int32, device="cuda")
+        cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+        ovf = torch.empty(1, dtype=torch.int32, device="cuda")
+        Q.nlist_build(tree, cfg.rcut, cfg.skin, 256, nbr, cnt, ovf)
+        torch.cuda.synchronize()
+        out.append((nbr, cnt, int(ovf.item())))
+        Q.qbvh_free(tree)
+    assert torch.equal(out[0][1], out[1][1]) and out[0][2] == out[1][2]
+    assert torch.equal(out[0][0], out[1][0])

@@ -282,6 +282,51 @@ def test_layout_traversal_reproduces_brute_force(leaf_size, qbits):
     assert b["records"].shape[0] == kept
 
 
+@pytest.mark.parametrize("leaf_size,radius", [(16, 2.3), (16, 0.5), (6, 1.0)])
+def test_cost_collapse_layout_traversal_reproduces_brute_force(leaf_size, radius):
+    cfg = W.lj_fluid(350, seed=8, rho=0.6, rc=2.0, skin=0.3)
+    b = LR.build_all(cfg.pos, cfg.box, leaf_size=leaf_size, collapse_radius=radius)
+    r2 = oracle.rlist2_table(cfg.rcut, cfg.skin)
+    perm = b["perm"].astype(np.int64)
+    rows = _alg1_rows(b["records"], b["ropes"], b["meta"], cfg.box, r2, np.zeros(cfg.n, np.int64),
+                      b["sorted_pos"], perm, b["sorted_pos"], perm, np.zeros(cfg.n, np.int64))
+    rp, cols = oracle.neighbor_lists(cfg.pos, cfg.box, cfg.rcut, cfg.skin, method="brute")
+    for k in range(cfg.n):
+        assert rows[k] == cols[rp[perm[k]]:rp[perm[k] + 1]].tolist()
+    # runs are whole collapsed subtrees of at most leaf_size particles covering every particle once
+    left, right = b["records"][:, 6].view(np.int32), b["records"][:, 7].view(np.int32)
+    covered = np.zeros(cfg.n, np.int64)
+    for ref in np.concatenate([left[left < 0], right[right < 0]]):
+        f, c = _run(ref)
+        assert 1 <= c <= leaf_size and (c == 1 or (f, f + c - 1) in b["trees"][0])
+        covered[f:f + c] += 1
+    assert np.all(covered == 1)
+
+
+def test_cost_collapse_reduces_to_the_size_rule_for_large_radii():
+    # with spheres far larger than any node, every box grows to about the same
+    # volume V: a subtree of c particles then costs c V as a run and at least
+    # (4 + c) V split, so every subtree of at most leaf_size particles collapses
+    cfg = W.lj_fluid(800, seed=11)
+    for leaf_size in (2, 8, 16):
+        a = LR.build_all(cfg.pos, cfg.box, leaf_size=leaf_size)
+        b = LR.build_all(cfg.pos, cfg.box, leaf_size=leaf_size, collapse_radius=1e6)
+        assert np.array_equal(a["records"], b["records"]) and np.array_equal(a["ropes"], b["ropes"])
+
+
+def test_cost_collapse_keeps_spread_subtrees_split():
+    # two tight clusters of 4 far apart inside one subtree of 8: split (two runs of 4)
+    # beats one run of 8 for small spheres, one run of 8 wins for large ones
+    pts = np.array([[1, 1, 1], [1.01, 1, 1], [1, 1.01, 1], [1.01, 1.01, 1],
+                    [5, 5, 5], [5.01, 5, 5], [5, 5.01, 5], [5.01, 5.01, 5]], np.float32)
+    box = np.full(3, 8.0, np.float32)
+    small = LR.build_all(pts, box, leaf_size=8, collapse_radius=0.1)
+    large = LR.build_all(pts, box, leaf_size=8, collapse_radius=50.0)
+    assert small["records"].shape[0] == 1 and large["records"].shape[0] == 0
+    runs = sorted(_run(int(np.int32(np.uint32(w)))) for w in small["records"][0, 6:8])
+    assert runs == [(0, 4), (4, 4)]
+
+
 def test_layout_two_types_and_empty_type():
     pos, box = W.uniform(300, [9.0, 9.0, 9.0], seed=13)
     types = (np.arange(300) % 4 == 0).astype(np.int32) * 2  # types 0 and 2, type 1 empty

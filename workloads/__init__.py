@@ -314,6 +314,37 @@ def near_cutoff_pairs_f64(n_base: int, n_pairs: int, box: float, r_list: float, 
                   skin=0.0, name=f"near_cutoff_f64_N{x.shape[0]}", meta={"seed": seed})
 
 
+def compact_type_f64(n_bulk: int = 3000, n_compact: int = 40, n_pairs: int = 400, box: float = 100.0,
+                     spread: float = 0.1, rc01: float = 2.5, seed=19010890,
+                     rel: tuple[float, float] = (1e-9, 1e-6)) -> Config:
+    """fp64 two-type case with a compact second type: ``n_bulk`` uniform type-0
+    points in a cubic box of edge ``box`` and ``n_compact`` type-1 points within
+    ``spread`` sigma of a centre near the far corner (large coordinates round
+    to fp32 by the most).  For ``n_pairs`` type-1 points a type-0 partner sits
+    at rc01 (1 +- e) in a random direction, e log-uniform in ``rel``.
+    rcut = [[1.0, rc01], [rc01, 0.5]], skin 0."""
+    rng = np.random.default_rng(seed)
+    L = float(box)
+    bulk = rng.uniform(0.0, L, size=(n_bulk, 3))
+    centre = np.array([0.97, 0.96, 0.98]) * L
+    comp = centre + rng.uniform(-spread / 2, spread / 2, size=(n_compact, 3))
+    who = rng.integers(0, n_compact, size=n_pairs)
+    u = rng.normal(size=(n_pairs, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    e = np.exp(rng.uniform(np.log(rel[0]), np.log(rel[1]), size=n_pairs)) * rng.choice([-1.0, 1.0], size=n_pairs)
+    r = float(np.float32(rc01))
+    partner = comp[who] + u * (r * (1.0 + e))[:, None]
+    x = np.concatenate([bulk, partner, comp])
+    t = np.concatenate([np.zeros(n_bulk + n_pairs, np.int32), np.ones(n_compact, np.int32)])
+    x = np.mod(x, L)
+    x = np.where(x >= L, 0.0, x)
+    order = rng.permutation(x.shape[0])
+    rcut = np.array([[1.0, rc01], [rc01, 0.5]], np.float32)
+    return Config(pos=np.ascontiguousarray(x[order]), box=np.full(3, L), rcut=rcut, skin=0.0,
+                  types=np.ascontiguousarray(t[order]), name=f"compact_type_f64_N{x.shape[0]}",
+                  meta={"seed": seed})
+
+
 WCA_RC = 2.0 ** (1.0 / 6.0)
 
 
