@@ -71,7 +71,8 @@ enum {
     QBVH_ENOMEM = -3, /* device allocation failed */
     QBVH_EHIP = -4,   /* a HIP runtime call failed; qbvh_last_hip_error() has it */
     QBVH_EAGAIN = -5, /* server admission: the request does not fit right now */
-    QBVH_ENOTSUP = -6 /* valid request the library does not support */
+    QBVH_ENOTSUP = -6, /* valid request the library does not support */
+    QBVH_ENOSPACE = -7 /* nlist_build_noalloc: n needs more than QBVH_NOALLOC_BYTES of workspace */
 };
 
 #define QBVH_MAX_TYPES 4
@@ -384,6 +385,43 @@ QBVH_API int qbvh_server_stats(qbvh_server_t *srv, qbvh_server_stats_t *stats);
  * described above), then free the server and every session; leases end.
  * No other call on the server may run concurrently with it. */
 QBVH_API void qbvh_server_destroy(qbvh_server_t *srv);
+
+/* ------------------------------------------------------- without allocation */
+
+/* Size of the fixed workspace of nlist_build_noalloc (160 MiB on each GPU the
+ * library runs on; about 153.5 bytes per particle, so n up to about 1.09
+ * million: qbvh_workspace_bytes(n, ...) <= QBVH_NOALLOC_BYTES). */
+#define QBVH_NOALLOC_BYTES ((size_t)160 << 20)
+
+/*
+ * nlist_build_noalloc -- qbvh_build followed by nlist_build in one call that
+ * allocates no memory, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * The tree is built into a fixed workspace of QBVH_NOALLOC_BYTES that the
+ * library holds in its code object, one per GPU, from its first use on that
+ * GPU until the process ends; the call makes no hipMalloc, hipFree or other
+ * allocating call.  Because the next call overwrites that workspace, the tree
+ * is not kept: build and list are one call.
+ *
+ *   d_pos, d_type, n, ntypes, box, opts   as qbvh_build (fp32 data)
+ *   rcut, skin, max_nbr, d_nbr, d_count, d_overflow   as nlist_build
+ *
+ * Outputs are those of qbvh_build + nlist_build with the same arguments,
+ * entry for entry.  Errors as those two calls, plus QBVH_ENOSPACE when n needs
+ * more workspace than QBVH_NOALLOC_BYTES (nothing is launched then).
+ * opts->validate = 1 synchronizes the stream, as in qbvh_build.
+ *
+ * Every call on one GPU uses that GPU's one workspace: calls ordered on one
+ * stream are safe, but calls whose work overlaps on one GPU (different
+ * streams or threads without ordering between them) race and give wrong
+ * lists.  The first call on a GPU looks up the workspace's device address
+ * (a runtime query, no allocation).
+ */
+QBVH_API int nlist_build_noalloc(const float *d_pos, const int32_t *d_type, int32_t n, int32_t ntypes,
+                    const float box[3], const qbvh_opts_t *opts, const float *rcut, float skin,
+                    int32_t max_nbr, int32_t *d_nbr, int32_t *d_count, int32_t *d_overflow,
+                    qbvh_stream_t stream);
 
 /* Release a handle (waits for its pending work).  NULL is ignored. */
 QBVH_API void qbvh_free(qbvh_t *tree);

@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqbvh.so")
 
 MAX_TYPES = 4
-OK, EINVAL, EGEOM, ENOMEM, EHIP, EAGAIN, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EGEOM, ENOMEM, EHIP, EAGAIN, ENOTSUP, ENOSPACE = 0, -1, -2, -3, -4, -5, -6, -7
+NOALLOC_BYTES = 160 << 20  # QBVH_NOALLOC_BYTES
 EXPORT = dict(keys=1, perm=2, sorted=3, left=4, right=5, range_f=6, range_l=7, parent=8,
               leaf_parent=9, box_lo=10, box_hi=11, records=12, ropes=13)
 
@@ -26,7 +27,7 @@ C_API = ("qbvh_build", "qbvh_build_f64", "nlist_build", "nlist_build_ex", "nlist
          "qbvh_server_create", "qbvh_server_submit", "qbvh_server_poll", "qbvh_server_wait",
          "qbvh_server_result", "qbvh_server_release", "qbvh_server_stats", "qbvh_server_destroy",
          "qbvh_free", "qbvh_strerror", "qbvh_last_hip_error", "qbvh_workspace_bytes", "qbvh_info",
-         "qbvh_export", "nlist_build_grid", "qgrid_free")
+         "qbvh_export", "nlist_build_grid", "qgrid_free", "nlist_build_noalloc")
 
 
 class QbvhError(RuntimeError):
@@ -119,6 +120,9 @@ def lib():
             L.nlist_build.restype = ctypes.c_int
             L.nlist_build_ex.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_float, I32, I32, P, P, P, P]
             L.nlist_build_ex.restype = ctypes.c_int
+            L.nlist_build_noalloc.argtypes = [P, P, I32, I32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(QbvhOpts),
+                                              ctypes.POINTER(ctypes.c_float), ctypes.c_float, I32, P, P, P, P]
+            L.nlist_build_noalloc.restype = ctypes.c_int
             L.nlist_build_many.argtypes = [I32, ctypes.POINTER(QbvhSystem), ctypes.POINTER(QbvhBatchOpts), P]
             L.nlist_build_many.restype = ctypes.c_int
             L.nlist_batch_stats.argtypes = [P, ctypes.POINTER(QbvhBatchStats)]
@@ -270,6 +274,26 @@ def nlist_build_ex(tree: Tree, rcut, skin: float, max_nbr: int, mode: int, nbr, 
                                _stream(stream))
     del rc
     _check(rc_, "nlist_build_ex")
+
+
+def nlist_build_noalloc(pos, types, box, ntypes: int, rcut, skin: float, max_nbr: int, nbr, count, overflow,
+                        opts=None, stream=None) -> None:
+    """qbvh_build + nlist_build in one call on the library's fixed workspace (no allocation)."""
+    import torch
+    n = int(pos.shape[0]) if pos is not None else 0
+    if pos is not None and (pos.dim() != 2 or pos.shape[1] != 3):
+        raise ValueError("pos must have shape [n, 3]")
+    b = (ctypes.c_float * 3)(*[float(x) for x in np.asarray(box, dtype=np.float32).reshape(3)])
+    o = _opts(opts)
+    rc, rp = _rcut_array(rcut, int(ntypes))
+    rc_ = lib().nlist_build_noalloc(_dev_ptr(pos, torch.float32, "pos", allow_none=True),
+                                    _dev_ptr(types, torch.int32, "types", allow_none=True), n, int(ntypes), b,
+                                    ctypes.byref(o) if o is not None else None, rp, float(skin), int(max_nbr),
+                                    _dev_ptr(nbr, torch.int32, "nbr", allow_none=True),
+                                    _dev_ptr(count, torch.int32, "count"),
+                                    _dev_ptr(overflow, torch.int32, "overflow"), _stream(stream))
+    del rc
+    _check(rc_, "nlist_build_noalloc")
 
 
 def nlist_build_many(systems, opts=None, stream=None) -> None:

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -127,6 +128,7 @@ const char *qbvh_strerror(int code) {
     case QBVH_EHIP: return "HIP runtime error";
     case QBVH_EAGAIN: return "request does not fit the server budget now";
     case QBVH_ENOTSUP: return "not supported";
+    case QBVH_ENOSPACE: return "n needs more than the fixed no-allocation workspace (QBVH_NOALLOC_BYTES)";
     default: return "unknown error";
     }
 }
@@ -194,6 +196,32 @@ int check_valid(const int32_t *d_err, hipStream_t s) {
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e);
     return err ? QBVH_EINVAL : QBVH_OK;
+}
+
+// The traversal of a built workspace into the caller's outputs; `a` carries
+// the list radii, the box and (fp64 data) the sorted fp64 positions.
+int launch_list(const Workspace &w, int32_t n, int32_t ntypes, const qbvh_opts_t &o, qbi::TravArgs &a,
+                int32_t max_nbr, int32_t mode, int32_t *d_nbr, int32_t *d_count, int32_t *d_overflow,
+                hipStream_t s) {
+    a.records = w.records;
+    a.ropes = w.ropes;
+    a.sorted = w.sorted;
+    a.meta = w.meta;
+    a.nbr = d_nbr;
+    a.count = d_count;
+    a.overflow = d_overflow;
+    a.n = n;
+    a.ntypes = ntypes;
+    a.max_nbr = max_nbr;
+    a.qpw = o.queries_per_wave ? o.queries_per_wave : qbi::queries_per_wave(n);
+    a.qbits = o.qbits;
+    const bool vec4 = max_nbr > 0 && (max_nbr % 4) == 0 && (((uintptr_t)d_nbr) & 15u) == 0;
+    const bool paper = mode == QBVH_LIST_PAPER;
+    hipError_t e = hipSuccess;
+    if (paper) e = qbi::launch_qpoint(w, n, ntypes, o.qbits, a.lmax, s);
+    if (e == hipSuccess) e = qbi::launch_traverse(a, o.block_size, vec4, paper, w.qpoint, s);
+    if (e != hipSuccess) return hip_fail(e);
+    return QBVH_OK;
 }
 
 }  // namespace
@@ -293,32 +321,14 @@ int nlist_build_ex(const qbvh_t *tree, const float *rcut, float skin, int32_t ma
     int rc = tree->f64 ? list_radii(rcut, skin, tree->ntypes, tree->box64, a.rlist2)
                        : list_radii(rcut, skin, tree->ntypes, tree->box, a.rlist2);
     if (rc != QBVH_OK) return rc;
-    a.records = tree->ws.records;
-    a.ropes = tree->ws.ropes;
-    a.sorted = tree->ws.sorted;
-    a.meta = tree->ws.meta;
-    a.nbr = d_nbr;
-    a.count = d_count;
-    a.overflow = d_overflow;
     if (tree->f64) {
         qbi::fill_trav_box(a, tree->box64);
         a.sorted64 = tree->sorted64;
     } else {
         qbi::fill_trav_box(a, tree->box);
     }
-    a.n = tree->n;
-    a.ntypes = tree->ntypes;
-    a.max_nbr = max_nbr;
-    a.qpw = tree->opts.queries_per_wave ? tree->opts.queries_per_wave : qbi::queries_per_wave(tree->n);
-    a.qbits = tree->opts.qbits;
-    const bool vec4 = max_nbr > 0 && (max_nbr % 4) == 0 && (((uintptr_t)d_nbr) & 15u) == 0;
-    const bool paper = mode == QBVH_LIST_PAPER;
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipSuccess;
-    if (paper) e = qbi::launch_qpoint(tree->ws, tree->n, tree->ntypes, tree->opts.qbits, a.lmax, s);
-    if (e == hipSuccess) e = qbi::launch_traverse(a, tree->opts.block_size, vec4, paper, tree->ws.qpoint, s);
-    if (e != hipSuccess) return hip_fail(e);
-    return QBVH_OK;
+    return launch_list(tree->ws, tree->n, tree->ntypes, tree->opts, a, max_nbr, mode, d_nbr, d_count, d_overflow,
+                       (hipStream_t)stream);
 }
 
 int nlist_build(const qbvh_t *tree, const float *rcut, float skin, int32_t max_nbr, int32_t *d_nbr,
@@ -382,6 +392,83 @@ int qbvh_export(const qbvh_t *tree, int32_t what, void *d_dst, size_t dst_bytes,
     hipError_t e = hipMemcpyAsync(d_dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
     return QBVH_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ no allocation
+
+// The build workspace of nlist_build_noalloc: a fixed array in the library's
+// code object, so every GPU the library runs on holds one copy of it from the
+// library's first use on that GPU until the process ends.  Host code never
+// passes the name itself to the device (on the host it is only a stand-in);
+// it uses the device address taken once per device below.
+static __device__ __align__(256) unsigned char scratch[QBVH_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current.
+int scratch_address(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if (dev < 0 || dev >= kMaxDevices) return QBVH_ENOTSUP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e);
+        if (!ptr || (((uintptr_t)ptr) & 255u) != 0) return QBVH_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return QBVH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nlist_build_noalloc(const float *d_pos, const int32_t *d_type, int32_t n, int32_t ntypes, const float box[3],
+                        const qbvh_opts_t *opts, const float *rcut, float skin, int32_t max_nbr, int32_t *d_nbr,
+                        int32_t *d_count, int32_t *d_overflow, qbvh_stream_t stream) {
+    // the checks of qbvh_build, then those of nlist_build
+    if (n < 0 || n > kMaxParticles || ntypes < 1 || ntypes > QBVH_MAX_TYPES || !box_ok(box)) return QBVH_EINVAL;
+    if (n > 0 && !d_pos) return QBVH_EINVAL;
+    if (n > 0 && ntypes > 1 && !d_type) return QBVH_EINVAL;
+    qbvh_opts_t o;
+    int rc = resolve_opts(opts, &o);
+    if (rc != QBVH_OK) return rc;
+    if (max_nbr < 0 || !d_overflow) return QBVH_EINVAL;
+    if (n > 0 && (!d_count || (max_nbr > 0 && !d_nbr))) return QBVH_EINVAL;
+    qbi::TravArgs a{};
+    rc = list_radii(rcut, skin, ntypes, box, a.rlist2);
+    if (rc != QBVH_OK) return rc;
+    const int32_t cap = n > 0 ? n : 1;
+    if (qbi::workspace_bytes(cap) > (size_t)QBVH_NOALLOC_BYTES) return QBVH_ENOSPACE;
+    void *base = nullptr;
+    rc = scratch_address(&base);
+    if (rc != QBVH_OK) return rc;
+
+    // every array the build reads is written by the build first (as for a
+    // tree rebuilt in place), so what an earlier call left needs no clearing
+    Workspace w;
+    qbi::workspace_carve(w, base, cap);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = qbi::launch_build(w, d_pos, ntypes > 1 ? d_type : nullptr, n, ntypes, box, o.leaf_size, o.qbits,
+                                     o.collapse_radius, o.validate, s);
+    if (e != hipSuccess) return hip_fail(e);
+    if (o.validate) {
+        rc = check_valid(w.err, s);
+        if (rc != QBVH_OK) return rc;
+    }
+    qbi::fill_trav_box(a, box);
+    return launch_list(w, n, ntypes, o, a, max_nbr, QBVH_LIST_EXACT, d_nbr, d_count, d_overflow, s);
 }
 
 }  // extern "C"

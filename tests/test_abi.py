@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror_and_codes():
     assert Q.qbvh_strerror(0) == "ok"
-    for code in (capi.EINVAL, capi.EGEOM, capi.ENOMEM, capi.EHIP, capi.EAGAIN, capi.ENOTSUP):
+    for code in (capi.EINVAL, capi.EGEOM, capi.ENOMEM, capi.EHIP, capi.EAGAIN, capi.ENOTSUP, capi.ENOSPACE):
         assert Q.qbvh_strerror(code) not in ("ok", "unknown error")
     assert Q.qbvh_strerror(12345) == "unknown error"
 
@@ -160,3 +160,35 @@ def test_package_does_not_import_the_oracle():
         if fn.endswith(".py"):
             src = open(os.path.join(pkg, fn)).read()
             assert not re.search(r"^\s*(import|from)\s+oracle\b", src, flags=re.M), fn
+
+
+def _noalloc_rc(n=100, ntypes=1, box=(10.0, 10.0, 10.0), rcut=(3.0,), skin=0.4, max_nbr=64, pos=16, typ=0,
+                nbr=16, count=16, overflow=16, opts=None):
+    """nlist_build_noalloc with placeholder device pointers: every case below is
+    rejected by the host checks, before any device call."""
+    lib = Q.lib()
+    b = (ctypes.c_float * 3)(*box)
+    rc = (ctypes.c_float * len(rcut))(*rcut)
+    o = capi._opts(opts)
+    P = ctypes.c_void_p
+    return lib.nlist_build_noalloc(P(pos) if pos else None, P(typ) if typ else None, n, ntypes, b,
+                                   ctypes.byref(o) if o is not None else None, rc, skin, max_nbr,
+                                   P(nbr) if nbr else None, P(count) if count else None,
+                                   P(overflow) if overflow else None, None)
+
+
+@pytest.mark.parametrize("kwargs,code", [
+    (dict(n=-1), capi.EINVAL),
+    (dict(ntypes=5), capi.EINVAL),
+    (dict(pos=0), capi.EINVAL),
+    (dict(ntypes=2, rcut=(1.0, 1.0, 1.0, 1.0)), capi.EINVAL),  # types missing
+    (dict(opts={"leaf_size": 17}), capi.EINVAL),
+    (dict(max_nbr=-1), capi.EINVAL),
+    (dict(overflow=0), capi.EINVAL),
+    (dict(count=0), capi.EINVAL),
+    (dict(rcut=(4.8,)), capi.EGEOM),
+    (dict(n=1_200_000, box=(200.0, 200.0, 200.0)), capi.ENOSPACE),  # past the fixed workspace
+])
+def test_noalloc_rejects_before_device_work(kwargs, code):
+    assert _noalloc_rc(**kwargs) == code
+    assert Q.qbvh_workspace_bytes(1_100_000) > Q.NOALLOC_BYTES >= Q.qbvh_workspace_bytes(1_090_000)
