@@ -166,14 +166,18 @@ def band_report(cfg, queries=None, threads: int = 0) -> dict:
 # factor the same counters read for a plain elementwise copy of known size (the
 # --copy-probe-mib kernel).  Valid only for the kernel sources it was taken on:
 # ``traffic`` is reported as null once their hash differs.
-TRAFFIC = {"sources": "2882763f409fd6ad", "workload": "lj8m",
+TRAFFIC = {"sources": "5b2f2a2ccaea31c4", "workload": "lj8m",
            "opts": {"leaf_size": 16, "qbits": 16, "block_size": 64},
-           "fetch_kib": 1611209.25, "write_kib": 6669795.15, "copy_factor": 1.0,
-           "fetch_factor": 0.500017, "profile": "profiles/k_traverse_lj8m_counters.md",
-           # SQ_ACTIVE_INST_VALU / (SIMDs x kernel cycles / 4): the VALU issues one wave64
+           "fetch_kib": 1611883.0, "write_kib": 6670154.3, "copy_factor": 1.0,
+           # FETCH_SIZE per byte read: 0.500 for vector loads (the copy probe), 1.000 for
+           # scalar loads (profiles/fetch_size_calibration.md)
+           "fetch_factor": 0.500013, "fetch_factor_scalar": 1.000049,
+           "profile": "profiles/k_traverse_lj8m_counters.md",
+           # SQ_INSTS_VALU x 4 / (1024 SIMDs x kernel cycles): the VALU issues one wave64
            # instruction per 4 cycles per SIMD, so this is the kernel's VALU issue roofline
-           "valu_busy": 0.89}
-KERNEL_SOURCES = ("paper_1901_08088_amd/csrc/traverse.hip", "paper_1901_08088_amd/csrc/qbvh_internal.h")
+           "valu_busy": 0.90}
+KERNEL_SOURCES = ("paper_1901_08088_amd/csrc/traverse.hip", "paper_1901_08088_amd/csrc/qbvh_internal.h",
+                  "paper_1901_08088_amd/csrc/build_common.h")
 
 
 def _code_only(text: str) -> str:
@@ -193,13 +197,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, opts: dict):
+def measured_traffic(workload: str, opts: dict, scalar_reads: bool = False):
+    """HBM bytes per traversal launch from the committed counter summary, or None
+    when the kernel sources, workload or options differ from the profiled ones.
+    Each counter is scaled by what it reads for the copy probe (FETCH_SIZE counts
+    half of the bytes read by vector loads, WRITE_SIZE all bytes written);
+    scalar_reads: scale FETCH_SIZE as for scalar loads instead (which it counts
+    in full), the lower end of the range."""
     t = TRAFFIC
     if t is None or t["sources"] != kernel_source_hash() or t["workload"] != workload or t["opts"] != opts:
         return None
-    # each counter scaled by what it reads for the copy probe (FETCH_SIZE counts
-    # half of the bytes read on this part, WRITE_SIZE all bytes written)
-    return (t["fetch_kib"] / t["fetch_factor"] + t["write_kib"] / t["copy_factor"]) * 1024.0
+    ff = t["fetch_factor_scalar"] if scalar_reads else t["fetch_factor"]
+    return (t["fetch_kib"] / ff + t["write_kib"] / t["copy_factor"]) * 1024.0
 
 
 def copy_probe(mib: int) -> None:
@@ -846,6 +855,7 @@ def main(argv=None) -> int:
         "roofline": {"kernel": "k_traverse", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, opts),
+                     "traffic_if_reads_scalar": measured_traffic(args.workload, opts, scalar_reads=True),
                      "valu_busy": (TRAFFIC["valu_busy"] if measured_traffic(args.workload, opts) is not None
                                    else None),
                      "algorithmic_bytes": tbytes, "kernel_sources": kernel_source_hash()},
