@@ -359,25 +359,30 @@ __device__ __forceinline__ int32_t xcd_logical_block() {
     return (int32_t)(xcd * qq + (xcd < rr ? xcd : rr) + (b >> 3));
 }
 
-// Query order.  A system of one type takes its queries in sorted (Z) order.
-// In a system of several types, the workgroups form eight equal stretches
-// (one per XCD when the system covers the whole launch); stretch x takes the
-// x-th eighth of every type's queries, smallest type first.  A sparse type's
+// Query order.  A system of one type takes its queries in sorted (Z) order,
+// a.qpw per wavefront.  In a system of several types, the workgroups form
+// eight equal stretches (one per XCD when the system covers the whole
+// launch); stretch x takes the x-th eighth of every type's queries, smallest
+// type first, in wavefronts of type_qpw queries of one type.  A sparse type's
 // wavefronts span the widest regions and run longest: this way they start
-// first and are spread over the stretches instead of closing the launch on
-// one XCD.  `wg` is the system's workgroup in dispatch order and `nwg` its
-// workgroup count (trav_blocks); returns the lane's position in the system, or
-// a.n for a lane past its stretch's share.
+// first, are spread over the stretches, and each takes few queries, instead
+// of closing the launch on one XCD.  `wg` is the system's workgroup in
+// dispatch order and `nwg` its workgroup count (trav_blocks, an upper bound
+// for several types); returns the lane's position in the system, or a.n for
+// an idle lane.
 template <int kBlock, class Args>
 __device__ __forceinline__ int32_t query_position(Args &a, const TreeMeta *__restrict__ meta, int32_t wg,
                                                   int32_t nwg) {
-    // wavefronts of a.qpw queries: lanes past a.qpw idle
-    const int32_t qpw = a.qpw, lane = (int32_t)(threadIdx.x & 63u), wave = (int32_t)(threadIdx.x >> 6);
-    if (lane >= qpw) return a.n;
-    if (a.ntypes <= 1) return (wg * (kBlock / 64) + wave) * qpw + lane;
+    const int32_t lane = (int32_t)(threadIdx.x & 63u), wave = (int32_t)(threadIdx.x >> 6);
+    if (a.ntypes <= 1) {
+        // wavefronts of a.qpw queries: lanes past a.qpw idle
+        const int32_t qpw = a.qpw;
+        if (lane >= qpw) return a.n;
+        return (wg * (kBlock / 64) + wave) * qpw + lane;
+    }
     const int32_t per = nwg / 8;
     const int64_t part = wg / per;
-    int32_t j = ((wg % per) * (kBlock / 64) + wave) * qpw + lane;
+    int32_t wi = (wg % per) * (kBlock / 64) + wave;  // wavefront of the stretch
     for (int r = 0; r < a.ntypes; ++r) {
         // the type of rank r by (count, type index)
         int t = 0;
@@ -389,8 +394,13 @@ __device__ __forceinline__ int32_t query_position(Args &a, const TreeMeta *__res
         }
         const int64_t len = meta[t].count;
         const int32_t lo = (int32_t)(len * part / 8), hi = (int32_t)(len * (part + 1) / 8);
-        if (j < hi - lo) return meta[t].start - a.start + lo + j;
-        j -= hi - lo;
+        const int32_t qt = type_qpw(len, a.n, a.qpw);
+        const int32_t nw = (hi - lo + qt - 1) / qt;
+        if (wi < nw) {
+            const int32_t j = wi * qt + lane;
+            return (lane < qt && j < hi - lo) ? meta[t].start - a.start + lo + j : a.n;
+        }
+        wi -= nw;
     }
     return a.n;
 }
