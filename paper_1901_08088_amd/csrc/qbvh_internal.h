@@ -135,7 +135,7 @@ struct BatchLaunch {
 // Z-consecutive queries lie far apart, so a wavefront of many of them walks a
 // very wide union and runs far longer than the others; such a type takes at
 // most kSparseQpw queries per wavefront.
-constexpr int32_t kSparseQpw = 8;
+constexpr int32_t kSparseQpw = 16;
 __host__ __device__ inline int32_t type_qpw(int64_t count, int64_t n, int32_t qpw) {
     return (count * 8 < n && qpw > kSparseQpw) ? kSparseQpw : qpw;
 }
