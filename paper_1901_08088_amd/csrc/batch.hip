@@ -77,29 +77,14 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_type_count(int32_t nsys, co
     type_count[i] = (uint32_t)(type_start(keys, y.off, y.off + y.n, t + 1) - type_start(keys, y.off, y.off + y.n, t));
 }
 
-// Sorted particle k of system s as float4 (x, y, z, bits of ~local input index).
-__global__ __launch_bounds__(kBuildThreads) void k_b_gather(const int32_t *__restrict__ blk_first, int32_t nsys,
-                                                            const SysBuild *__restrict__ sysb,
-                                                            const uint32_t *__restrict__ vals,
-                                                            float4 *__restrict__ sorted) {
-    const Item it = item_of(blk_first, nsys);
-    const SysBuild &y = sysb[it.sys];
-    if (it.local >= y.n) return;
-    const int32_t k = y.off + it.local;
-    const int32_t li = (int32_t)vals[k] - y.off;
-    float4 p;
-    p.x = y.pos[3 * (int64_t)li + 0];
-    p.y = y.pos[3 * (int64_t)li + 1];
-    p.z = y.pos[3 * (int64_t)li + 2];
-    p.w = __int_as_float(~li);
-    sorted[k] = p;
-}
-
+// Radix tree of every system (k_karras per system), together with the gather:
+// sorted particle k of system s as float4 (x, y, z, bits of ~local input index).
 __global__ __launch_bounds__(kBuildThreads) void k_b_karras(const int32_t *__restrict__ blk_first, int32_t nsys,
                                                             const SysBuild *__restrict__ sysb,
                                                             const uint32_t *__restrict__ keys,
                                                             const uint32_t *__restrict__ type_count,
-                                                            int32_t leaf_size, int32_t *__restrict__ left,
+                                                            int32_t leaf_size, const uint32_t *__restrict__ vals,
+                                                            float4 *__restrict__ sorted, int32_t *__restrict__ left,
                                                             int32_t *__restrict__ right, int32_t *__restrict__ rf,
                                                             int32_t *__restrict__ rl, int32_t *__restrict__ parent,
                                                             int32_t *__restrict__ leaf_parent,
@@ -111,21 +96,27 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_karras(const int32_t *__res
     const StagedKeys K = stage_keys(keys, s_keys, y.off + it.local - (int32_t)threadIdx.x, y.off, y.off + y.n);
     if (it.local >= y.n) return;
     const int32_t i = y.off + it.local;
+    // the particle of sorted position i in Z order (the gather), its loads
+    // overlapping the searches below
+    const int32_t li = (int32_t)vals[i] - y.off;
+    const float4 p = make_float4(y.pos[3 * (int64_t)li + 0], y.pos[3 * (int64_t)li + 1], y.pos[3 * (int64_t)li + 2],
+                                 __int_as_float(~li));
     const Segment g = batch_segment(keys[i], y.off, type_count + it.sys * QBVH_MAX_TYPES);
     visit[i] = 0;
     if (i == g.e - 1) {  // no internal node carries the last position's id
         if (g.e - g.s == 1) leaf_parent[i] = -1;
-        return;
+    } else {
+        const KarrasNode r = karras_node(K, i, g);
+        left[i] = r.left;
+        right[i] = r.right;
+        rf[i] = r.f;
+        rl[i] = r.l;
+        if (r.left < 0) leaf_parent[r.gamma] = i; else parent[r.gamma] = i;
+        if (r.right < 0) leaf_parent[r.gamma + 1] = i; else parent[r.gamma + 1] = i;
+        if (i == g.s) parent[i] = -1;
+        if (r.l - r.f + 1 > leaf_size) atomicAdd(&kept[r.f], 1u);
     }
-    const KarrasNode r = karras_node(K, i, g);
-    left[i] = r.left;
-    right[i] = r.right;
-    rf[i] = r.f;
-    rl[i] = r.l;
-    if (r.left < 0) leaf_parent[r.gamma] = i; else parent[r.gamma] = i;
-    if (r.right < 0) leaf_parent[r.gamma + 1] = i; else parent[r.gamma + 1] = i;
-    if (i == g.s) parent[i] = -1;
-    if (r.l - r.f + 1 > leaf_size) atomicAdd(&kept[r.f], 1u);
+    sorted[i] = p;
 }
 
 // Tree description of every (system, type).
@@ -202,11 +193,9 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t s) {
     hipLaunchKernelGGL(k_b_type_count, dim3((unsigned)((ninit + kBuildThreads - 1) / kBuildThreads)),
                        dim3(kBuildThreads), 0, s, b.nsys, b.sysb, w.keys, b.type_count);
     if (b.total > 0) {
-        hipLaunchKernelGGL(k_b_gather, dim3((unsigned)b.blocks), dim3(kBuildThreads), 0, s, b.blk_first, b.nsys,
-                           b.sysb, w.vals, w.sorted);
         hipLaunchKernelGGL(k_b_karras, dim3((unsigned)b.blocks), dim3(kBuildThreads), 0, s, b.blk_first, b.nsys,
-                           b.sysb, w.keys, b.type_count, b.leaf_size, w.left, w.right, w.rf, w.rl, w.parent,
-                           w.leaf_parent, w.visit, w.kept);
+                           b.sysb, w.keys, b.type_count, b.leaf_size, w.vals, w.sorted, w.left, w.right, w.rf,
+                           w.rl, w.parent, w.leaf_parent, w.visit, w.kept);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = launch_fit(w, b.total, Collapse{0.f, 0.f, 0.f, b.leaf_size}, s);

@@ -70,20 +70,6 @@ __global__ void k_type_count(const uint32_t *__restrict__ keys, int32_t n, uint3
         type_count[t] = (uint32_t)(type_start(keys, 0, n, t + 1) - type_start(keys, 0, n, t));
 }
 
-__global__ __launch_bounds__(kBuildThreads) void k_gather(const float *__restrict__ pos,
-                                                          const uint32_t *__restrict__ vals, int32_t n,
-                                                          float4 *__restrict__ sorted) {
-    const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
-    if (k >= n) return;
-    const uint32_t i = vals[k];
-    float4 p;
-    p.x = pos[3 * (int64_t)i + 0];
-    p.y = pos[3 * (int64_t)i + 1];
-    p.z = pos[3 * (int64_t)i + 2];
-    p.w = __int_as_float(~(int32_t)i);
-    sorted[k] = p;
-}
-
 // fp64 particle data, before the build: each coordinate rounded to nearest
 // fp32 (the tree is built and walked on these; the exact decisions use the
 // fp64 values), with the fp64 checks 0 <= x < L and 0 <= type < ntypes when
@@ -127,10 +113,16 @@ __global__ __launch_bounds__(kBuildThreads) void k_gather64(const float4 *__rest
 
 // Karras's parallel construction: internal node i of a segment covers a
 // range with i at one end; its direction, far end and split are found by
-// exponential then binary search on the common-prefix length.
+// exponential then binary search on the common-prefix length.  The same
+// thread also writes sorted position i's particle in Z order (the gather):
+// its loads from the unsorted input go out first and complete while the
+// searches run, so the gather's memory latency and the searches' VALU work
+// overlap in one launch instead of following each other.
 __global__ __launch_bounds__(kBuildThreads) void k_karras(const uint32_t *__restrict__ keys, int32_t n,
                                                           int32_t ntypes, const uint32_t *__restrict__ type_count,
-                                                          int32_t leaf_size, int32_t *__restrict__ left,
+                                                          int32_t leaf_size, const float *__restrict__ pos,
+                                                          const uint32_t *__restrict__ vals,
+                                                          float4 *__restrict__ sorted, int32_t *__restrict__ left,
                                                           int32_t *__restrict__ right, int32_t *__restrict__ rf,
                                                           int32_t *__restrict__ rl, int32_t *__restrict__ parent,
                                                           int32_t *__restrict__ leaf_parent,
@@ -139,22 +131,26 @@ __global__ __launch_bounds__(kBuildThreads) void k_karras(const uint32_t *__rest
     const StagedKeys K = stage_keys(keys, s_keys, (int32_t)(blockIdx.x * kBuildThreads), 0, n);
     const int32_t i = blockIdx.x * kBuildThreads + threadIdx.x;
     if (i >= n) return;
+    const uint32_t o = vals[i];
+    const float4 p = make_float4(pos[3 * (int64_t)o + 0], pos[3 * (int64_t)o + 1], pos[3 * (int64_t)o + 2],
+                                 __int_as_float(~(int32_t)o));
     const Segment g = segment_of(keys[i], n, ntypes, type_count);
     visit[i] = 0;
     if (i == g.e - 1) {  // no internal node carries the last position's id
         if (g.e - g.s == 1) leaf_parent[i] = -1;
-        return;
+    } else {
+        const KarrasNode r = karras_node(K, i, g);
+        const int32_t gamma = r.gamma, f = r.f, la = r.l, cl = r.left, cr = r.right;
+        left[i] = cl;
+        right[i] = cr;
+        rf[i] = f;
+        rl[i] = la;
+        if (cl < 0) leaf_parent[gamma] = i; else parent[gamma] = i;
+        if (cr < 0) leaf_parent[gamma + 1] = i; else parent[gamma + 1] = i;
+        if (i == g.s) parent[i] = -1;
+        if (la - f + 1 > leaf_size) atomicAdd(&kept[f], 1u);
     }
-    const KarrasNode r = karras_node(K, i, g);
-    const int32_t gamma = r.gamma, f = r.f, la = r.l, cl = r.left, cr = r.right;
-    left[i] = cl;
-    right[i] = cr;
-    rf[i] = f;
-    rl[i] = la;
-    if (cl < 0) leaf_parent[gamma] = i; else parent[gamma] = i;
-    if (cr < 0) leaf_parent[gamma + 1] = i; else parent[gamma + 1] = i;
-    if (i == g.s) parent[i] = -1;
-    if (la - f + 1 > leaf_size) atomicAdd(&kept[f], 1u);
+    sorted[i] = p;
 }
 
 // Bottom-up boxes (Section 2.1: boxes are fit by walking up the tree from the
@@ -659,11 +655,10 @@ hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d
     if (e != hipSuccess) return e;
     if (ntypes > 1) hipLaunchKernelGGL(k_type_count, dim3(1), dim3(64), 0, s, w.keys, n, w.type_count);
     if (n > 0) {
-        hipLaunchKernelGGL(k_gather, grid_for(n), dim3(kBuildThreads), 0, s, d_pos, w.vals, n, w.sorted);
-        // with the cost model, which nodes keep a record is known only after the fit
+        // (with the cost model, which nodes keep a record is known only after the fit)
         hipLaunchKernelGGL(k_karras, grid_for(n), dim3(kBuildThreads), 0, s, w.keys, n, ntypes, w.type_count,
-                           by_cost ? INT32_MAX : leaf_size, w.left, w.right, w.rf, w.rl, w.parent, w.leaf_parent,
-                           w.visit, w.kept);
+                           by_cost ? INT32_MAX : leaf_size, d_pos, w.vals, w.sorted, w.left, w.right, w.rf, w.rl,
+                           w.parent, w.leaf_parent, w.visit, w.kept);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = launch_fit(w, n, col, s);
