@@ -168,7 +168,7 @@ def band_report(cfg, queries=None, threads: int = 0) -> dict:
 # ``traffic`` is reported as null once their hash differs.
 TRAFFIC = {"sources": "7817567816a80622", "workload": "lj8m",
            "opts": {"leaf_size": 16, "qbits": 16, "block_size": 64},
-           "fetch_kib": 1528805.0, "write_kib": 6615588.0, "copy_factor": 1.0,
+           "fetch_kib": 1527511.0, "write_kib": 6616178.0, "copy_factor": 1.0,
            # FETCH_SIZE per byte read: 0.500 for vector loads (the copy probe), 1.000 for
            # scalar loads (profiles/fetch_size_calibration.md)
            "fetch_factor": 0.500013, "fetch_factor_scalar": 1.000049,
