@@ -166,9 +166,9 @@ def band_report(cfg, queries=None, threads: int = 0) -> dict:
 # factor the same counters read for a plain elementwise copy of known size (the
 # --copy-probe-mib kernel).  Valid only for the kernel sources it was taken on:
 # ``traffic`` is reported as null once their hash differs.
-TRAFFIC = {"sources": "7817567816a80622", "workload": "lj8m",
+TRAFFIC = {"sources": "6fdd282cd350e3c5", "workload": "lj8m",
            "opts": {"leaf_size": 16, "qbits": 16, "block_size": 64},
-           "fetch_kib": 1527511.0, "write_kib": 6616178.0, "copy_factor": 1.0,
+           "fetch_kib": 1527441.0, "write_kib": 6610877.0, "copy_factor": 1.0,
            # FETCH_SIZE per byte read: 0.500 for vector loads (the copy probe), 1.000 for
            # scalar loads (profiles/fetch_size_calibration.md)
            "fetch_factor": 0.500013, "fetch_factor_scalar": 1.000049,
@@ -177,7 +177,7 @@ TRAFFIC = {"sources": "7817567816a80622", "workload": "lj8m",
            # instruction per 4 cycles per SIMD, so this is the kernel's VALU issue roofline
            "valu_busy": 0.90}
 KERNEL_SOURCES = ("paper_1901_08088_amd/csrc/traverse.hip", "paper_1901_08088_amd/csrc/qbvh_internal.h",
-                  "paper_1901_08088_amd/csrc/build_common.h")
+                  "paper_1901_08088_amd/csrc/build_common.h", "paper_1901_08088_amd/csrc/launch_geometry.h")
 
 
 def _code_only(text: str) -> str:

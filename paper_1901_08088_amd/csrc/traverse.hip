@@ -393,9 +393,9 @@ __device__ __forceinline__ int32_t query_position(Args &a, const TreeMeta *__res
             if (rank == r) t = u;
         }
         const int64_t len = meta[t].count;
-        const int32_t lo = (int32_t)(len * part / 8), hi = (int32_t)(len * (part + 1) / 8);
+        const int32_t lo = stretch_lo(len, part), hi = stretch_lo(len, part + 1);
         const int32_t qt = type_qpw(len, a.n, a.qpw);
-        const int32_t nw = (hi - lo + qt - 1) / qt;
+        const int32_t nw = type_waves(len, a.n, a.qpw, part);
         if (wi < nw) {
             const int32_t j = wi * qt + lane;
             return (lane < qt && j < hi - lo) ? meta[t].start - a.start + lo + j : a.n;
