@@ -2,7 +2,8 @@
 density 0.85, rc 3.0 + skin 0.4, max_nbr 256), of the 1M WCA fluid (short
 cutoff) and of the 1M spinodal-like liquid-vapor configuration, in the launch
 configuration the benchmark times: every count against the oracle's cell list,
-and complete rows for a seeded sample of particles."""
+and complete rows for a seeded sample of particles; at 1M, every row of
+every single-system configuration."""
 import numpy as np
 import pytest
 
@@ -71,3 +72,39 @@ def test_raw_rows_are_deterministic_at_1m(kind):
         Q.qbvh_free(tree)
     assert torch.equal(out[0][1], out[1][1]) and out[0][2] == out[1][2]
     assert torch.equal(out[0][0], out[1][0])
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("kind", ["lj", "wca", "spinodal", "colloid"])
+def test_every_row_at_1m(kind):
+    # every row of the full-size 1M configurations against the oracle's cell
+    # list, entry for entry as sets (rows sorted on both sides), in the launch
+    # configuration the benchmark times
+    torch = require_gpu()
+    cfg = {"lj": W.lj_fluid, "wca": W.wca_fluid, "spinodal": W.spinodal,
+           "colloid": W.colloid_solvent}[kind](1_000_000)
+    n, max_nbr = cfg.n, 256
+    print(f"[scale] every row {kind} N={n}", flush=True)
+    pos = torch.from_numpy(cfg.pos).cuda()
+    types = None if cfg.types is None else torch.from_numpy(cfg.types).cuda()
+    tree = Q.qbvh_build(pos, types, cfg.box, cfg.ntypes, BENCH_OPTS)
+    nbr = torch.empty((n, max_nbr), dtype=torch.int32, device="cuda")
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    ovf = torch.empty(1, dtype=torch.int32, device="cuda")
+    Q.nlist_build(tree, cfg.rcut, cfg.skin, max_nbr, nbr, cnt, ovf)
+    torch.cuda.synchronize()
+    gcnt = cnt.cpu().numpy().astype(np.int64)
+    rp, cols = oracle.neighbor_lists(cfg.pos, cfg.box, cfg.rcut, cfg.skin, types=cfg.types)
+    ocnt = np.diff(rp)
+    assert np.array_equal(gcnt, ocnt), f"{int(np.count_nonzero(gcnt != ocnt))} count mismatches"
+    assert int(ovf.item()) == 0 and int(ocnt.max()) <= max_nbr
+    g = nbr.cpu().numpy()
+    del nbr
+    listed = np.arange(max_nbr)[None, :] < gcnt[:, None]
+    rows = np.repeat(np.arange(n, dtype=np.int64), gcnt)
+    gkey = (rows << 32) | g[listed].astype(np.int64)
+    del g, listed
+    gkey.sort()
+    okey = (rows << 32) | cols.astype(np.int64)
+    assert np.array_equal(gkey, okey), f"{int(np.count_nonzero(gkey != okey))} entries differ"
+    print(f"[scale] every row {kind} N={n}: {gkey.size} entries equal", flush=True)
