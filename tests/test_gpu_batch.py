@@ -137,8 +137,8 @@ def test_batch_full_ensemble():
     """The 256-replica ensemble at full size (N log-uniform in [2000, 200000],
     density 0.3-0.9, rc 2.5-3.0, skin 0.4, max_nbr 256), graph-replayed after
     tuning: every count of every replica equals the oracle's (and the
-    single-system path's), and sampled rows of every replica equal the
-    oracle's."""
+    single-system path's), sampled rows of every replica and every row of
+    every eighth replica equal the oracle's."""
     torch = require_gpu()
     cfgs = W.ensemble()
     total = sum(c.n for c in cfgs)
@@ -153,6 +153,7 @@ def test_batch_full_ensemble():
     rows = {c.name: np.sort(rng.choice(c.n, min(12, c.n), replace=False)) for c in cfgs}
     res = batch_results(systems, cfgs, rows=rows)
     plain = _plain_counts(cfgs, 256)
+    checked = 0
     for k, c in enumerate(cfgs):
         nbr, cnt, ovf = res[k]
         ocnt = oracle.neighbor_counts(c.pos, c.box, c.rcut, c.skin, method="cells")
@@ -165,6 +166,11 @@ def test_batch_full_ensemble():
         full = np.full((c.n, 256), -7, np.int32)
         full[q] = nbr
         compare_rows(c, full, cnt, ovf, 256, queries=q, method="cells")
+        if k % 8 == 0:
+            # every row of every eighth replica
+            compare_rows(c, systems[k]["nbr"].cpu().numpy()[:c.n, :256], cnt, ovf, 256, method="cells")
+            checked += c.n
+    print(f"[batch] every row of 32 replicas ({checked:,} particles) equal to the oracle's", flush=True)
     print(f"[batch] stats {Q.nlist_batch_stats()}", flush=True)
     del systems
     torch.cuda.empty_cache()
