@@ -450,7 +450,12 @@ __global__ __launch_bounds__(kBuildThreads) void k_kept_collapse(int32_t n, int3
     if (keep) atomicAdd(&kept[f], 1u);
 }
 
-// One record per kept internal node (Karras id i).
+// One record per kept internal node (Karras id i).  Only about one id in
+// leaf_size keeps a record, so a workgroup first collects the kept ids of
+// kEmitItems x kBuildThreads consecutive ids into LDS (one ballot per wave and
+// step) and then writes their records with every lane busy.
+constexpr int kEmitItems = 8;
+
 __global__ __launch_bounds__(kBuildThreads) void k_emit(int32_t n, int32_t ntypes,
                                                         const uint32_t *__restrict__ keys,
                                                         const uint32_t *__restrict__ type_count,
@@ -465,16 +470,39 @@ __global__ __launch_bounds__(kBuildThreads) void k_emit(int32_t n, int32_t ntype
                                                         const TreeMeta *__restrict__ meta, int32_t leaf_size,
                                                         const uint32_t *__restrict__ kept_flag, int32_t qbits,
                                                         uint4 *__restrict__ records, int32_t *__restrict__ ropes) {
-    const int32_t i = blockIdx.x * kBuildThreads + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t key = keys[i];
-    const Segment g = segment_of(key, n, ntypes, type_count);
-    if (i >= g.e - 1) return;  // not an internal node id
-    const int32_t f = rf[i], l = rl[i];
-    if (kept_flag ? kept_flag[i] == 0u : l - f + 1 <= leaf_size) return;  // inside a particle run
-    const TreeMeta &m = meta[ntypes == 1 ? 0 : (key >> 30)];
-    emit_record(i, f, l, m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, kept_flag, qbits,
-                records, ropes);
+    __shared__ int32_t s_ids[kEmitItems * kBuildThreads];
+    __shared__ uint32_t s_count;
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
+    const int32_t lane = (int32_t)__lane_id();
+    const int64_t b0 = (int64_t)blockIdx.x * (kEmitItems * kBuildThreads);
+#pragma unroll
+    for (int k = 0; k < kEmitItems; ++k) {
+        const int64_t i = b0 + k * kBuildThreads + threadIdx.x;
+        bool keep = false;
+        if (i < n) {
+            const Segment g = segment_of(ntypes == 1 ? 0u : keys[i], n, ntypes, type_count);
+            // an internal node id outside every particle run
+            if (i < g.e - 1)
+                keep = kept_flag ? kept_flag[i] != 0u : rl[i] - rf[i] + 1 > leaf_size;
+        }
+        const uint64_t m = __ballot(keep);
+        if (m == 0) continue;
+        uint32_t at = 0;
+        if (lane == 0) at = atomicAdd(&s_count, (uint32_t)__popcll(m));
+        at = (uint32_t)__shfl((int32_t)at, 0);
+        const uint32_t below =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (keep) s_ids[at + below] = (int32_t)i;
+    }
+    __syncthreads();
+    const uint32_t count = s_count;
+    for (uint32_t e = threadIdx.x; e < count; e += kBuildThreads) {
+        const int32_t i = s_ids[e];
+        const TreeMeta &m = meta[ntypes == 1 ? 0 : (keys[i] >> 30)];
+        emit_record(i, rf[i], rl[i], m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, kept_flag,
+                    qbits, records, ropes);
+    }
 }
 
 // Cell box of every sorted particle in its type tree's grid (the leaf box of a
@@ -674,7 +702,8 @@ hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d
     hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, s, n, ntypes, w.type_count, w.sorted, w.box_lo, w.box_hi,
                        w.kept, qbits, leaf_size, by_cost ? w.cost : nullptr, ext_floor, w.meta);
     if (n > 0)
-        hipLaunchKernelGGL(k_emit, grid_for(n), dim3(kBuildThreads), 0, s, n, ntypes, w.keys, w.type_count,
+        hipLaunchKernelGGL(k_emit, grid_for((n + kEmitItems - 1) / kEmitItems), dim3(kBuildThreads), 0, s, n, ntypes,
+                           w.keys, w.type_count,
                            w.sorted, w.left, w.right, w.rf, w.rl, w.parent, w.box_lo, w.box_hi, w.kept, w.meta,
                            leaf_size, by_cost ? w.visit : nullptr, qbits, w.records, w.ropes);
     return hipGetLastError();

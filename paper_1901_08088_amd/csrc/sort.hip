@@ -343,14 +343,31 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_sort_tile(uint32_t *__re
 
 // ---------------------------------------------------------------- exclusive scan
 
+// A thread's kScanItems consecutive entries: two 16-byte loads when all are in
+// range (the array is 32-byte aligned, checked on the host), else one by one.
+__device__ __forceinline__ void load_items(const uint32_t *__restrict__ data, int64_t base, int32_t len,
+                                           uint32_t (&v)[kScanItems]) {
+    static_assert(kScanItems == 8, "two 16-byte loads per thread");
+    if (base + kScanItems <= len) {
+        const uint4 a = reinterpret_cast<const uint4 *>(data + base)[0];
+        const uint4 b = reinterpret_cast<const uint4 *>(data + base)[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < len) ? data[base + k] : 0u;
+    }
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__restrict__ data, int32_t len,
                                                               uint32_t *__restrict__ partials) {
     __shared__ uint32_t lds[kScanThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    load_items(data, base, len, v);
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < len) s += data[base + k];
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
     uint32_t tot;
     (void)block_exclusive_scan<kScanThreads>(s, lds, tot);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -399,18 +416,25 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(uint32_t *__restrict
     __shared__ uint32_t lds[kScanThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
+    load_items(data, base, len, v);
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = (base + k < len) ? data[base + k] : 0u;
-        s += v[k];
-    }
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
     uint32_t tot;
     uint32_t ex = block_exclusive_scan<kScanThreads>(s, lds, tot) + partials[blockIdx.x];
+    uint32_t o[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < len) data[base + k] = ex;
+        o[k] = ex;
         ex += v[k];
+    }
+    if (base + kScanItems <= len) {
+        reinterpret_cast<uint4 *>(data + base)[0] = make_uint4(o[0], o[1], o[2], o[3]);
+        reinterpret_cast<uint4 *>(data + base)[1] = make_uint4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < len) data[base + k] = o[k];
     }
 }
 
@@ -478,6 +502,7 @@ hipError_t launch_exclusive_scan(uint32_t *data, int32_t len, uint32_t *partials
         hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanThreads), 0, s, data, len);
         return hipGetLastError();
     }
+    if ((reinterpret_cast<uintptr_t>(data) & 31u) != 0) return hipErrorInvalidValue;
     const int32_t nb = scan_blocks(len);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, data, len, partials);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nb);
