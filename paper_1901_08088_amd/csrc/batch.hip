@@ -77,48 +77,6 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_type_count(int32_t nsys, co
     type_count[i] = (uint32_t)(type_start(keys, y.off, y.off + y.n, t + 1) - type_start(keys, y.off, y.off + y.n, t));
 }
 
-// Radix tree of every system (k_karras per system), together with the gather:
-// sorted particle k of system s as float4 (x, y, z, bits of ~local input index).
-__global__ __launch_bounds__(kBuildThreads) void k_b_karras(const int32_t *__restrict__ blk_first, int32_t nsys,
-                                                            const SysBuild *__restrict__ sysb,
-                                                            const uint32_t *__restrict__ keys,
-                                                            const uint32_t *__restrict__ type_count,
-                                                            int32_t leaf_size, const uint32_t *__restrict__ vals,
-                                                            float4 *__restrict__ sorted, int32_t *__restrict__ left,
-                                                            int32_t *__restrict__ right, int32_t *__restrict__ rf,
-                                                            int32_t *__restrict__ rl, int32_t *__restrict__ parent,
-                                                            int32_t *__restrict__ leaf_parent,
-                                                            uint32_t *__restrict__ visit, uint32_t *__restrict__ kept) {
-    __shared__ uint32_t s_keys[3 * kBuildThreads];
-    const Item it = item_of(blk_first, nsys);
-    const SysBuild &y = sysb[it.sys];
-    // the block's first position: blocks never straddle systems
-    const StagedKeys K = stage_keys(keys, s_keys, y.off + it.local - (int32_t)threadIdx.x, y.off, y.off + y.n);
-    if (it.local >= y.n) return;
-    const int32_t i = y.off + it.local;
-    // the particle of sorted position i in Z order (the gather), its loads
-    // overlapping the searches below
-    const int32_t li = (int32_t)vals[i] - y.off;
-    const float4 p = make_float4(y.pos[3 * (int64_t)li + 0], y.pos[3 * (int64_t)li + 1], y.pos[3 * (int64_t)li + 2],
-                                 __int_as_float(~li));
-    const Segment g = batch_segment(keys[i], y.off, type_count + it.sys * QBVH_MAX_TYPES);
-    visit[i] = 0;
-    if (i == g.e - 1) {  // no internal node carries the last position's id
-        if (g.e - g.s == 1) leaf_parent[i] = -1;
-    } else {
-        const KarrasNode r = karras_node(K, i, g);
-        left[i] = r.left;
-        right[i] = r.right;
-        rf[i] = r.f;
-        rl[i] = r.l;
-        if (r.left < 0) leaf_parent[r.gamma] = i; else parent[r.gamma] = i;
-        if (r.right < 0) leaf_parent[r.gamma + 1] = i; else parent[r.gamma + 1] = i;
-        if (i == g.s) parent[i] = -1;
-        if (r.l - r.f + 1 > leaf_size) atomicAdd(&kept[r.f], 1u);
-    }
-    sorted[i] = p;
-}
-
 // Tree description of every (system, type).
 __global__ __launch_bounds__(64) void k_b_meta(int32_t nsys, const SysBuild *__restrict__ sysb,
                                                const uint32_t *__restrict__ type_count,
@@ -163,18 +121,36 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_emit(const int32_t *__restr
                                                           const TreeMeta *__restrict__ meta, int32_t leaf_size,
                                                           int32_t qbits, uint4 *__restrict__ records,
                                                           int32_t *__restrict__ ropes) {
+    // the workgroup's kept ids first (about one in leaf_size), so that the
+    // record writes run on full wavefronts
+    __shared__ int32_t s_ids[kBuildThreads];
+    __shared__ uint32_t s_count;
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
     const Item it = item_of(blk_first, nsys);
     const SysBuild &y = sysb[it.sys];
-    if (it.local >= y.n) return;
     const int32_t i = y.off + it.local;
-    const uint32_t key = keys[i];
-    const Segment g = batch_segment(key, y.off, type_count + it.sys * QBVH_MAX_TYPES);
-    if (i >= g.e - 1) return;  // not an internal node id
-    const int32_t f = rf[i], l = rl[i];
-    if (l - f + 1 <= leaf_size) return;  // inside a particle run
-    const TreeMeta &m = meta[it.sys * QBVH_MAX_TYPES + (key >> 30)];
-    emit_record(i, f, l, m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, nullptr, qbits, records,
-                ropes);
+    bool keep = false;
+    if (it.local < y.n) {
+        const Segment g = batch_segment(keys[i], y.off, type_count + it.sys * QBVH_MAX_TYPES);
+        // an internal node id outside every particle run
+        if (i < g.e - 1) keep = rl[i] - rf[i] + 1 > leaf_size;
+    }
+    const uint64_t mk = __ballot(keep);
+    if (mk != 0) {
+        uint32_t at = 0;
+        if (__lane_id() == 0) at = atomicAdd(&s_count, (uint32_t)__popcll(mk));
+        at = (uint32_t)__shfl((int32_t)at, 0);
+        const uint32_t below =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+        if (keep) s_ids[at + below] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x >= s_count) return;
+    const int32_t k = s_ids[threadIdx.x];
+    const TreeMeta &m = meta[it.sys * QBVH_MAX_TYPES + (keys[k] >> 30)];
+    emit_record(k, rf[k], rl[k], m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, nullptr, qbits,
+                records, ropes);
 }
 
 }  // namespace
@@ -193,12 +169,8 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t s) {
     hipLaunchKernelGGL(k_b_type_count, dim3((unsigned)((ninit + kBuildThreads - 1) / kBuildThreads)),
                        dim3(kBuildThreads), 0, s, b.nsys, b.sysb, w.keys, b.type_count);
     if (b.total > 0) {
-        hipLaunchKernelGGL(k_b_karras, dim3((unsigned)b.blocks), dim3(kBuildThreads), 0, s, b.blk_first, b.nsys,
-                           b.sysb, w.keys, b.type_count, b.leaf_size, w.vals, w.sorted, w.left, w.right, w.rf,
-                           w.rl, w.parent, w.leaf_parent, w.visit, w.kept);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        e = launch_fit(w, b.total, Collapse{0.f, 0.f, 0.f, b.leaf_size}, s);
+        e = launch_tree(w, b.total, TreeSource{nullptr, b.sysb, b.sys_off, b.nsys}, b.leaf_size,
+                        Collapse{0.f, 0.f, 0.f, b.leaf_size}, s);
         if (e != hipSuccess) return e;
     }
     e = launch_exclusive_scan(w.kept, b.total + 1, b.scan_part, s);

@@ -111,77 +111,102 @@ __global__ __launch_bounds__(kBuildThreads) void k_gather64(const float4 *__rest
     o[3] = 0.0;
 }
 
-// Karras's parallel construction: internal node i of a segment covers a
-// range with i at one end; its direction, far end and split are found by
-// exponential then binary search on the common-prefix length.  The same
-// thread also writes sorted position i's particle in Z order (the gather):
-// its loads from the unsorted input go out first and complete while the
-// searches run, so the gather's memory latency and the searches' VALU work
-// overlap in one launch instead of following each other.
-__global__ __launch_bounds__(kBuildThreads) void k_karras(const uint32_t *__restrict__ keys, int32_t n,
-                                                          int32_t ntypes, const uint32_t *__restrict__ type_count,
-                                                          int32_t leaf_size, const float *__restrict__ pos,
-                                                          const uint32_t *__restrict__ vals,
-                                                          float4 *__restrict__ sorted, int32_t *__restrict__ left,
-                                                          int32_t *__restrict__ right, int32_t *__restrict__ rf,
-                                                          int32_t *__restrict__ rl, int32_t *__restrict__ parent,
-                                                          int32_t *__restrict__ leaf_parent,
-                                                          uint32_t *__restrict__ visit, uint32_t *__restrict__ kept) {
-    __shared__ uint32_t s_keys[3 * kBuildThreads];
-    const StagedKeys K = stage_keys(keys, s_keys, (int32_t)(blockIdx.x * kBuildThreads), 0, n);
-    const int32_t i = blockIdx.x * kBuildThreads + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t o = vals[i];
-    const float4 p = make_float4(pos[3 * (int64_t)o + 0], pos[3 * (int64_t)o + 1], pos[3 * (int64_t)o + 2],
-                                 __int_as_float(~(int32_t)o));
-    const Segment g = segment_of(keys[i], n, ntypes, type_count);
-    visit[i] = 0;
-    if (i == g.e - 1) {  // no internal node carries the last position's id
-        if (g.e - g.s == 1) leaf_parent[i] = -1;
-    } else {
-        const KarrasNode r = karras_node(K, i, g);
-        const int32_t gamma = r.gamma, f = r.f, la = r.l, cl = r.left, cr = r.right;
-        left[i] = cl;
-        right[i] = cr;
-        rf[i] = f;
-        rl[i] = la;
-        if (cl < 0) leaf_parent[gamma] = i; else parent[gamma] = i;
-        if (cr < 0) leaf_parent[gamma + 1] = i; else parent[gamma + 1] = i;
-        if (i == g.s) parent[i] = -1;
-        if (la - f + 1 > leaf_size) atomicAdd(&kept[f], 1u);
-    }
-    sorted[i] = p;
-}
-
-// Bottom-up boxes (Section 2.1: boxes are fit by walking up the tree from the
-// leaves).  Every leaf climbs; at each internal node an atomic visit counter
-// lets the first arrival stop and the second merge both children and go on.
+// Radix tree and node boxes in one bottom-up pass (Section 2.1: the hierarchy
+// over the Z-ordered particles, its boxes fit from the leaves up).  The tree
+// is the binary radix tree of the augmented keys (key, position): the split
+// between sorted positions k and k + 1 has the weight delta(k), the common
+// prefix length of the two augmented keys (-1 where k and k + 1 lie in
+// different type trees), and every node's range [l, r] is bounded by two
+// splits of smaller weight than any inside it.  So a node's parent is found
+// from its two bounding splits alone: the heavier one (they never tie) is the
+// parent's split.  A node that is the left child of its parent's split ends
+// at that split, r = split, and takes r as its id; a right child starts just
+// after it and takes l; the root of a tree takes its first position.  These
+// are the ids of Karras's top-down construction (an internal node's range has
+// its id at one end), which the tree is node for node; here no node searches
+// for its range: every leaf climbs, and at each parent split an exchange lets
+// the first arrival leave its far end and stop while the second merges both
+// children and goes on (the agglomerative order of Apetrei's construction).
 //
-// The counters are synchronized within one workgroup only: an agent-scope
-// acquire/release on gfx950 writes back and invalidates the XCD's L2 at every
-// step, which is far too slow for N atomic steps.  So the climb is split by
-// sorted position into chunks.  A node whose particle range lies inside one
-// chunk has both children inside it, so only that chunk's workgroup ever
-// touches its counter.  Level 0 uses chunks of kFitChunk positions with
-// counters and boxes in LDS (60 KB, so two workgroups share a compute unit);
-// every further level multiplies the chunk by
-// kFitFanout and climbs in global memory with workgroup-scope atomics,
-// starting from the nodes the previous level left at its chunk borders (the
-// "frontier": finished nodes whose parent straddles a border).  The last
-// level has one chunk and reaches every root.  A frontier holds at most two
-// border chains of the tree (each at most 65 deep), so kFrontierCap suffices.
+// The climb is split by sorted position into chunks, so that an exchange and
+// the child boxes it hands over are synchronized within one workgroup: a
+// split's two children meet only in a chunk holding both its neighbours.  (An
+// agent-scope acquire/release on gfx950 writes back and invalidates the XCD's
+// L2 at every step, far too slow for N atomic steps.)  The first level takes
+// chunks of kFitChunk positions with keys, split weights, particles, boxes and
+// exchange slots in LDS; every further level multiplies the chunk by
+// kFitFanout and climbs in global memory from the nodes the level before left
+// at its chunk borders (the "frontier": finished nodes whose parent did not
+// finish there).  The last level has one chunk and reaches every root.  The
+// unfinished nodes of a chunk nest along its two borders (a radix tree over
+// 32-bit keys plus 32-bit positions has at most 64 internal levels) and each
+// has at most one finished child in the chunk, so kFrontierCap suffices.
 constexpr int kFitChunk = 1024;
 constexpr int kFitThreads = 1024;
 // A small fanout keeps every level's climbs short (about five tree levels from
 // each frontier node) and its workgroups many; N = 8M takes three level launches.
 constexpr int kFitFanout = 32;
 constexpr int kFrontierCap = 160;
-// A chunk's frontier holds nodes whose parent's range crosses one of the
-// chunk's two borders; the nodes whose range crosses a border form one chain
-// of the tree (they nest), so each border contributes at most one node per
-// tree level.  Keys are 32 bits plus a 32-bit position, so a radix tree has
-// at most 64 levels of internal nodes: 2 * (64 + 1) entries at most.
 static_assert(kFrontierCap >= 2 * (64 + 1), "fit frontier bound");
+// A level's climbs stop at most once each on a first arrival.
+constexpr int kPendCap = kFitFanout * kFrontierCap;
+// Exchange slot states besides a far end (a sorted position, >= 0).
+constexpr int32_t kSlotEmpty = -1;
+constexpr int32_t kSlotDone = -2;
+
+// Sorted position i's particle (x, y, z, bits of ~input index within its system).
+__device__ __forceinline__ float4 gather_particle(const TreeSource &src, const uint32_t *__restrict__ vals, int32_t i) {
+    const uint32_t o = vals[i];
+    if (src.sysb == nullptr)
+        return make_float4(src.pos[3 * (int64_t)o + 0], src.pos[3 * (int64_t)o + 1], src.pos[3 * (int64_t)o + 2],
+                           __int_as_float(~(int32_t)o));
+    const SysBuild &y = src.sysb[find_seg(src.sys_off, src.nsys, i)];
+    const int32_t li = (int32_t)o - y.off;
+    return make_float4(y.pos[3 * (int64_t)li + 0], y.pos[3 * (int64_t)li + 1], y.pos[3 * (int64_t)li + 2],
+                       __int_as_float(~li));
+}
+
+// Weight of the split between sorted positions k and k + 1 (both < n) with
+// keys ka and kb: -1 across a type or a system boundary, else the common
+// prefix length of the augmented keys (equal keys differ in the position).
+__device__ __forceinline__ int32_t split_delta(const TreeSource &src, int32_t k, uint32_t ka, uint32_t kb) {
+    if ((ka ^ kb) >> 30) return -1;
+    if (src.sysb != nullptr) {
+        const int32_t s = find_seg(src.sys_off, src.nsys, k);
+        if (k + 1 >= src.sys_off[s + 1]) return -1;
+    }
+    return ka != kb ? (int32_t)__clz(ka ^ kb) : 32 + (int32_t)__clz((uint32_t)(k ^ (k + 1)));
+}
+
+// What the climb writes: the tree's node arrays (by Karras id), the Z-ordered
+// particles, the kept-node counts, and the split weights and exchange slots
+// the upper levels use.
+struct TreeOut {
+    float4 *sorted;
+    int32_t *left, *right, *rf, *rl, *parent, *leaf_parent;
+    float4 *box_lo, *box_hi;
+    uint32_t *kept;   // kept[l] counts the nodes [l, r] longer than kept_leaf
+    float *cost;      // cost model only
+    int32_t *delta;   // [n]: delta[k] for k < n - 1, delta[n - 1] = -1
+    int32_t *slot;    // [n]: exchange slot of each split
+    int32_t kept_leaf;
+};
+
+// Everything about a finished internal node K = [l, r] with children cl, cr.
+template <bool kCost>
+__device__ __forceinline__ void write_node(const TreeOut &o, int32_t K, int32_t l, int32_t r, int32_t cl, int32_t cr,
+                                           const float lo[3], const float hi[3], float cst) {
+    o.rf[K] = l;
+    o.rl[K] = r;
+    o.left[K] = cl;
+    o.right[K] = cr;
+    o.box_lo[K] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+    o.box_hi[K] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+    if (kCost) o.cost[K] = cst;
+    if (cl < 0) o.leaf_parent[~cl] = K; else o.parent[cl] = K;
+    if (cr < 0) o.leaf_parent[~cr] = K; else o.parent[cr] = K;
+    if (r - l + 1 > o.kept_leaf) atomicAdd(&o.kept[l], 1u);
+}
 
 __device__ __forceinline__ void frontier_push(int32_t c, uint32_t *s_fcount, int32_t *s_front, int32_t *err) {
     const uint32_t slot = atomicAdd(s_fcount, 1u);
@@ -191,148 +216,214 @@ __device__ __forceinline__ void frontier_push(int32_t c, uint32_t *s_fcount, int
         atomicOr(err, 2);
 }
 
-// First level: the chunk's node links, its particles' positions, the visit
-// counters and the boxes all live in LDS (loaded with coalesced reads), so a
-// climb touches global memory only to read its leaf's parent.
+// The child of split g whose far end is e: the left child [e, g] or the right
+// child [g + 1, e], as a node id or a leaf (~position).
+__device__ __forceinline__ int32_t child_at(int32_t g, int32_t e) {
+    return e <= g ? (e == g ? ~g : g) : (e == g + 1 ? ~(g + 1) : g + 1);
+}
+
+// A node of the climb: range, bounding split weights, box, cost and children.
+struct Climb {
+    int32_t l, r, dl, dr, cl, cr;
+    float lo[3], hi[3];
+    float cost;
+};
+
+// First level: one chunk of kFitChunk sorted positions per workgroup; also
+// gathers the chunk's particles in Z order and leaves its split weights and
+// cleared exchange slots for the upper levels.  A node finished here has its
+// id, range and children inside the chunk, so everything written about it
+// (its range, split and box, its children's parent, the kept counts) is
+// collected in LDS and written out at the end with coalesced stores.
+constexpr int32_t kUnset = INT32_MIN;
+
 template <bool kCost>
-__global__ __launch_bounds__(kFitThreads) void k_fit_local(const float4 *__restrict__ sorted,
-                                                           const int32_t *__restrict__ left,
-                                                           const int32_t *__restrict__ right,
-                                                           const int32_t *__restrict__ rf,
-                                                           const int32_t *__restrict__ rl,
-                                                           const int32_t *__restrict__ parent,
-                                                           const int32_t *__restrict__ leaf_parent, int32_t n,
-                                                           float4 *__restrict__ box_lo, float4 *__restrict__ box_hi,
-                                                           int32_t *__restrict__ front, uint32_t *__restrict__ fcount,
-                                                           int32_t *err, Collapse col, float *__restrict__ cost) {
-    __shared__ float s_box[6][kFitChunk];
-    __shared__ float s_cost[kCost ? kFitChunk : 1];
+__global__ __launch_bounds__(kFitThreads) void k_tree_local(const uint32_t *__restrict__ keys,
+                                                            const uint32_t *__restrict__ vals, int32_t n,
+                                                            TreeSource src, TreeOut out, int32_t *__restrict__ front,
+                                                            uint32_t *__restrict__ fcount, int32_t *err,
+                                                            Collapse col) {
+    __shared__ uint32_t s_keykept[kFitChunk + 2];  // keys c0 - 1 .. c0 + m, then kept counts by l - c0
+    __shared__ int32_t s_delta[kFitChunk + 1];     // s_delta[j]: weight of split c0 - 1 + j
     __shared__ float s_pos[3][kFitChunk];
-    __shared__ int32_t s_link[5][kFitChunk];  // left, right, range first, range last, parent
-    __shared__ uint32_t s_visit[kFitChunk];
+    __shared__ float s_box[6][kFitChunk];          // nodes by id - c0
+    __shared__ float s_cost[kCost ? kFitChunk : 1];
+    __shared__ int32_t s_nl[kFitChunk], s_nr[kFitChunk], s_ng[kFitChunk];  // range and split (s_nr < 0: none)
+    __shared__ int32_t s_par[kFitChunk], s_lpar[kFitChunk];  // parent of node / leaf c0 + i
+    __shared__ int32_t s_slot[kFitChunk];          // by split - c0
     __shared__ int32_t s_front[kFrontierCap];
     __shared__ uint32_t s_fcount;
     const int32_t c0 = blockIdx.x * kFitChunk;
     const int32_t m = min(kFitChunk, n - c0);
-    for (int i = threadIdx.x; i < kFitChunk; i += kFitThreads) {
-        s_visit[i] = 0;
-        if (i < m) {
-            // entries of ids that are not internal nodes (the last position of
-            // a segment) are loaded but never referenced
-            const int32_t k = c0 + i;
-            s_link[0][i] = left[k];
-            s_link[1][i] = right[k];
-            s_link[2][i] = rf[k];
-            s_link[3][i] = rl[k];
-            s_link[4][i] = parent[k];
-            const float4 q = sorted[k];
-            s_pos[0][i] = q.x;
-            s_pos[1][i] = q.y;
-            s_pos[2][i] = q.z;
-        }
+    const int32_t t = threadIdx.x;
+    // the particle's loads go out first and complete while the keys are staged
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t < m) p = gather_particle(src, vals, c0 + t);
+    for (int32_t j = t; j < m + 2; j += kFitThreads) {
+        const int32_t k = c0 - 1 + j;
+        s_keykept[j] = (k >= 0 && k < n) ? keys[k] : 0u;
     }
-    if (threadIdx.x == 0) s_fcount = 0;
+    if (t < m) {
+        out.sorted[c0 + t] = p;
+        s_pos[0][t] = p.x;
+        s_pos[1][t] = p.y;
+        s_pos[2][t] = p.z;
+        s_slot[t] = kSlotEmpty;
+        s_nr[t] = -1;
+        s_par[t] = kUnset;
+        s_lpar[t] = kUnset;
+        out.slot[c0 + t] = kSlotEmpty;
+    }
+    if (t == 0) s_fcount = 0;
     __syncthreads();
-    for (int32_t i0 = threadIdx.x; i0 < m; i0 += kFitThreads) {
-        int32_t c = ~(c0 + i0);
-        int32_t p = leaf_parent[c0 + i0];
-        for (int step = 0; p >= 0 && step < kMaxDepth; ++step) {
-            const int32_t j = p - c0;
-            // a parent whose range leaves the chunk ends this level's climb
-            if (j < 0 || j >= m || s_link[2][j] < c0 || s_link[3][j] >= c0 + kFitChunk) {
-                frontier_push(c, &s_fcount, s_front, err);
-                break;
-            }
-            const uint32_t old = __hip_atomic_fetch_add(&s_visit[j], 1u, __ATOMIC_ACQ_REL,
-                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (old == 0) break;
-            float lo[3], hi[3];
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                const int32_t ch = s_link[side][j];
-                float clo[3], chi[3];
-                if (ch < 0) {
-                    const int32_t t = ~ch - c0;
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) clo[d] = chi[d] = s_pos[d][t];
-                } else {
-                    const int32_t t = ch - c0;
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        clo[d] = s_box[d][t];
-                        chi[d] = s_box[3 + d][t];
-                    }
-                }
+    for (int32_t j = t; j <= m; j += kFitThreads) {
+        const int32_t k = c0 - 1 + j;
+        const int32_t d = (k < 0 || k + 1 >= n) ? -1 : split_delta(src, k, s_keykept[j], s_keykept[j + 1]);
+        s_delta[j] = d;
+        if (k >= c0) out.delta[k] = d;  // this chunk's splits c0 .. c0 + m - 1
+    }
+    __syncthreads();
+    if (t < m) s_keykept[t] = 0u;
+    __syncthreads();
+    if (t < m) {
+        Climb u;
+        u.l = u.r = c0 + t;
+        u.dl = s_delta[t];
+        u.dr = s_delta[t + 1];
+        u.cl = u.cr = 0;
+        u.lo[0] = u.hi[0] = p.x;
+        u.lo[1] = u.hi[1] = p.y;
+        u.lo[2] = u.hi[2] = p.z;
+        u.cost = col.kVball;
+        int32_t split = 0;  // the split of the node being carried (internal nodes)
+        for (int step = 0; step < kMaxDepth; ++step) {
+            const bool leaf = u.l == u.r;
+            const bool root = u.dl < 0 && u.dr < 0;
+            const bool goes_left = u.dr > u.dl;  // the parent's split is r: this node is its left child
+            const int32_t K = leaf ? ~u.l : (goes_left && !root ? u.r : u.l);
+            if (!leaf) {
+                const int32_t k = K - c0;
+                s_nl[k] = u.l;
+                s_nr[k] = u.r;
+                s_ng[k] = split;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    lo[d] = side ? fminf(lo[d], clo[d]) : clo[d];
-                    hi[d] = side ? fmaxf(hi[d], chi[d]) : chi[d];
+                    s_box[d][k] = u.lo[d];
+                    s_box[3 + d][k] = u.hi[d];
                 }
+                if (kCost) s_cost[k] = u.cost;
+                if (u.cl < 0) s_lpar[~u.cl - c0] = K; else s_par[u.cl - c0] = K;
+                if (u.cr < 0) s_lpar[~u.cr - c0] = K; else s_par[u.cr - c0] = K;
+                if (u.r - u.l + 1 > out.kept_leaf) atomicAdd(&s_keykept[u.l - c0], 1u);
             }
+            if (root) {
+                if (leaf) s_lpar[u.l - c0] = -1; else s_par[K - c0] = -1;
+                break;
+            }
+            const int32_t g = goes_left ? u.r : u.l - 1;
+            if (g < c0 || g >= c0 + m - 1) {  // a split on or past the chunk's border
+                frontier_push(K, &s_fcount, s_front, err);
+                break;
+            }
+            const int32_t e = __hip_atomic_exchange(&s_slot[g - c0], goes_left ? u.l : u.r, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (e == kSlotEmpty) break;  // the sibling finishes the parent
+            s_slot[g - c0] = kSlotDone;
+            const int32_t sib = child_at(g, e);
+            float slo[3], shi[3], scost;
+            if (sib < 0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) slo[d] = shi[d] = s_pos[d][~sib - c0];
+                scost = col.kVball;
+            } else {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    slo[d] = s_box[d][sib - c0];
+                    shi[d] = s_box[3 + d][sib - c0];
+                }
+                scost = kCost ? fabsf(s_cost[sib - c0]) : 0.0f;
+            }
+            const float own = fabsf(u.cost);
+            if (goes_left) {
+                u.r = e;
+                u.dr = s_delta[e - c0 + 1];
+                u.cl = K;
+                u.cr = sib;
+            } else {
+                u.l = e;
+                u.dl = s_delta[e - c0];
+                u.cl = sib;
+                u.cr = K;
+            }
+            split = g;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                s_box[d][j] = lo[d];
-                s_box[3 + d][j] = hi[d];
+                u.lo[d] = fminf(u.lo[d], slo[d]);
+                u.hi[d] = fmaxf(u.hi[d], shi[d]);
             }
-            if (kCost) {
-                // children's costs: a particle, or an internal node of the chunk finished before
-                float fc[2];
-#pragma unroll
-                for (int side = 0; side < 2; ++side) {
-                    const int32_t ch = s_link[side][j];
-                    fc[side] = ch < 0 ? col.kVball : fabsf(s_cost[ch - c0]);
-                }
-                s_cost[j] = node_cost(col, s_link[3][j] - s_link[2][j] + 1, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2],
-                                      fc[0], fc[1]);
-            }
-            c = p;
-            p = s_link[4][j];
+            if (kCost)
+                u.cost = node_cost(col, u.r - u.l + 1, u.lo[0], u.lo[1], u.lo[2], u.hi[0], u.hi[1], u.hi[2],
+                                   goes_left ? own : scost, goes_left ? scost : own);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < m; i += kFitThreads) {
-        if (s_visit[i] == 2) {
-            box_lo[c0 + i] = make_float4(s_box[0][i], s_box[1][i], s_box[2][i], 0.0f);
-            box_hi[c0 + i] = make_float4(s_box[3][i], s_box[4][i], s_box[5][i], 0.0f);
-            if (kCost) cost[c0 + i] = s_cost[i];
-        }
+    // first arrivals whose sibling never came: their parent straddles a border
+    for (int32_t j = t; j < m - 1; j += kFitThreads) {
+        const int32_t e = s_slot[j];
+        if (e >= 0) frontier_push(child_at(c0 + j, e), &s_fcount, s_front, err);
     }
+    if (t < m) {
+        const int32_t K = c0 + t;
+        const int32_t r = s_nr[t];
+        if (r >= 0) {
+            const int32_t l = s_nl[t], g = s_ng[t];
+            out.rf[K] = l;
+            out.rl[K] = r;
+            out.left[K] = g == l ? ~l : g;
+            out.right[K] = g + 1 == r ? ~r : g + 1;
+            out.box_lo[K] = make_float4(s_box[0][t], s_box[1][t], s_box[2][t], 0.0f);
+            out.box_hi[K] = make_float4(s_box[3][t], s_box[4][t], s_box[5][t], 0.0f);
+            if (kCost) out.cost[K] = s_cost[t];
+        }
+        if (s_par[t] != kUnset) out.parent[K] = s_par[t];
+        if (s_lpar[t] != kUnset) out.leaf_parent[K] = s_lpar[t];
+        out.kept[K] = s_keykept[t];  // the chunk's own nodes are the only ones starting here so far
+    }
+    __syncthreads();
     const uint32_t fc = min(s_fcount, (uint32_t)kFrontierCap);
-    for (uint32_t i = threadIdx.x; i < fc; i += kFitThreads) front[(int64_t)blockIdx.x * kFrontierCap + i] = s_front[i];
-    if (threadIdx.x == 0) fcount[blockIdx.x] = fc;
+    for (uint32_t i = t; i < fc; i += kFitThreads) front[(int64_t)blockIdx.x * kFrontierCap + i] = s_front[i];
+    if (t == 0) fcount[blockIdx.x] = fc;
 }
 
-// One level above the first: chunks of `chunk` positions, starting from the
-// frontiers of the `fan` previous-level chunks each contains.
+// One level above the first: chunks of `chunk` positions, climbing from the
+// frontiers of the `fan` previous-level chunks each contains, with the
+// exchange slots in global memory (workgroup-scope atomics: a split's two
+// children meet in one chunk).  A step waits for two round trips: the
+// exchange, then the sibling's box with the new bounding weight.
 template <bool kCost>
-__global__ __launch_bounds__(kFitThreads) void k_fit_level(const float4 *__restrict__ sorted,
-                                                           const int32_t *__restrict__ left,
-                                                           const int32_t *__restrict__ right,
-                                                           const int32_t *__restrict__ rf,
-                                                           const int32_t *__restrict__ rl,
-                                                           const int32_t *__restrict__ parent,
-                                                           const int32_t *__restrict__ leaf_parent, int64_t chunk,
-                                                           int32_t nprev, const int32_t *__restrict__ front_in,
-                                                           const uint32_t *__restrict__ fcount_in, uint32_t *visit,
-                                                           float4 *box_lo, float4 *box_hi,
-                                                           int32_t *__restrict__ front_out,
-                                                           uint32_t *__restrict__ fcount_out, int32_t *err,
-                                                           Collapse col, float *cost) {
+__global__ __launch_bounds__(kFitThreads) void k_tree_level(int32_t n, int64_t chunk, int32_t nprev,
+                                                            const int32_t *__restrict__ front_in,
+                                                            const uint32_t *__restrict__ fcount_in, TreeOut out,
+                                                            int32_t *__restrict__ front_out,
+                                                            uint32_t *__restrict__ fcount_out, int32_t *err,
+                                                            Collapse col) {
     __shared__ int32_t s_front[kFrontierCap];
     __shared__ uint32_t s_fcount;
     __shared__ uint32_t s_off[kFitFanout + 1];
+    __shared__ int32_t s_pend[kPendCap];  // splits where a climb stopped as the first arrival
+    __shared__ uint32_t s_npend;
     const int64_t c0 = (int64_t)blockIdx.x * chunk;
-    const int64_t c1 = c0 + chunk;
+    const int64_t c1 = min(c0 + chunk, (int64_t)n);
     const int32_t j0 = blockIdx.x * kFitFanout;
     // The frontier entries of the fan-in chunks, numbered consecutively, so
-    // that each thread climbs from at most a few of them (the climbs are
-    // chains of dependent loads: their count per thread sets the time).
+    // that each thread climbs from at most a few of them.
     if (threadIdx.x < kFitFanout) {
         const int32_t jc = j0 + (int32_t)threadIdx.x;
         s_off[threadIdx.x + 1] = jc < nprev ? min(fcount_in[jc], (uint32_t)kFrontierCap) : 0u;
     }
     if (threadIdx.x == 0) {
         s_fcount = 0;
+        s_npend = 0;
         s_off[0] = 0;
     }
     __syncthreads();
@@ -347,41 +438,91 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_level(const float4 *__restr
             const int mid = (lo + hi) >> 1;
             if (s_off[mid] <= e) lo = mid; else hi = mid;
         }
-        const int32_t jc = j0 + lo;
-        const uint32_t slot = e - s_off[lo];
-        int32_t c = front_in[(int64_t)jc * kFrontierCap + slot];
-        int32_t p = c < 0 ? leaf_parent[~c] : parent[c];
-        for (int step = 0; p >= 0 && step < kMaxDepth; ++step) {
-            // The links do not change during the fit: all of them are read
-            // before the atomic, so that a step waits for three round trips
-            // (links, counter, child boxes) rather than five.
-            const int32_t pf = rf[p], pl = rl[p], c0i = left[p], c1i = right[p], pp = parent[p];
-            // (sign bits rather than compares: both loads are then waited for together)
-            if (((uint64_t)((int64_t)pf - c0) | (uint64_t)(c1 - 1 - (int64_t)pl)) >> 63) {
-                frontier_push(c, &s_fcount, s_front, err);
+        const int32_t c = front_in[(int64_t)(j0 + lo) * kFrontierCap + (e - s_off[lo])];
+        // the entry was written when its parent's split was found: restart there
+        Climb u;
+        u.cl = u.cr = 0;
+        if (c < 0) {
+            u.l = u.r = ~c;
+            const float4 q = out.sorted[~c];
+            u.lo[0] = u.hi[0] = q.x;
+            u.lo[1] = u.hi[1] = q.y;
+            u.lo[2] = u.hi[2] = q.z;
+            u.cost = col.kVball;
+        } else {
+            u.l = out.rf[c];
+            u.r = out.rl[c];
+            const float4 a = out.box_lo[c], b = out.box_hi[c];
+            u.lo[0] = a.x; u.lo[1] = a.y; u.lo[2] = a.z;
+            u.hi[0] = b.x; u.hi[1] = b.y; u.hi[2] = b.z;
+            u.cost = kCost ? out.cost[c] : 0.0f;
+        }
+        u.dl = u.l > 0 ? out.delta[u.l - 1] : -1;
+        u.dr = out.delta[u.r];
+        bool fresh = false;
+        for (int step = 0; step < kMaxDepth; ++step) {
+            const bool leaf = u.l == u.r;
+            const bool root = u.dl < 0 && u.dr < 0;
+            const bool goes_left = u.dr > u.dl;
+            const int32_t K = leaf ? ~u.l : (goes_left && !root ? u.r : u.l);
+            if (fresh) write_node<kCost>(out, K, u.l, u.r, u.cl, u.cr, u.lo, u.hi, u.cost);
+            if (root) {
+                out.parent[K] = -1;  // (a climb reaches a root only through a merge)
                 break;
             }
-            const uint32_t old = __hip_atomic_fetch_add(&visit[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (old == 0) break;
-            // a leaf child's box is its particle: pointers are selected, not
-            // branched on, so the four loads go out together
-            const float4 *pa_lo = c0i < 0 ? sorted + ~c0i : box_lo + c0i;
-            const float4 *pa_hi = c0i < 0 ? sorted + ~c0i : box_hi + c0i;
-            const float4 *pb_lo = c1i < 0 ? sorted + ~c1i : box_lo + c1i;
-            const float4 *pb_hi = c1i < 0 ? sorted + ~c1i : box_hi + c1i;
-            const float4 alo = *pa_lo, ahi = *pa_hi, blo = *pb_lo, bhi = *pb_hi;
-            const float4 nlo = make_float4(fminf(alo.x, blo.x), fminf(alo.y, blo.y), fminf(alo.z, blo.z), 0.0f);
-            const float4 nhi = make_float4(fmaxf(ahi.x, bhi.x), fmaxf(ahi.y, bhi.y), fmaxf(ahi.z, bhi.z), 0.0f);
-            box_lo[p] = nlo;
-            box_hi[p] = nhi;
-            if (kCost) {
-                const float fa = c0i < 0 ? col.kVball : fabsf(cost[c0i]);
-                const float fb = c1i < 0 ? col.kVball : fabsf(cost[c1i]);
-                cost[p] = node_cost(col, pl - pf + 1, nlo.x, nlo.y, nlo.z, nhi.x, nhi.y, nhi.z, fa, fb);
+            const int32_t g = goes_left ? u.r : u.l - 1;
+            if (g < c0 || g >= c1 - 1) {
+                frontier_push(K, &s_fcount, s_front, err);
+                break;
             }
-            c = p;
-            p = pp;
+            const int32_t ex = __hip_atomic_exchange(&out.slot[g], goes_left ? u.l : u.r, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (ex == kSlotEmpty) {
+                const uint32_t at = atomicAdd(&s_npend, 1u);
+                if (at < (uint32_t)kPendCap) s_pend[at] = g; else atomicOr(err, 2);
+                break;
+            }
+            out.slot[g] = kSlotDone;
+            const int32_t sib = child_at(g, ex);
+            // the sibling's box and cost and the new far weight, loaded together
+            const float4 *pa = sib < 0 ? out.sorted + ~sib : out.box_lo + sib;
+            const float4 *pb = sib < 0 ? out.sorted + ~sib : out.box_hi + sib;
+            const float4 slo = *pa, shi = *pb;
+            const float scost = kCost ? (sib < 0 ? col.kVball : fabsf(out.cost[sib])) : 0.0f;
+            const int32_t dnew = goes_left ? out.delta[ex] : (ex > 0 ? out.delta[ex - 1] : -1);
+            const float own = fabsf(u.cost);
+            if (goes_left) {
+                u.r = ex;
+                u.dr = dnew;
+                u.cl = K;
+                u.cr = sib;
+            } else {
+                u.l = ex;
+                u.dl = dnew;
+                u.cl = sib;
+                u.cr = K;
+            }
+            u.lo[0] = fminf(u.lo[0], slo.x);
+            u.lo[1] = fminf(u.lo[1], slo.y);
+            u.lo[2] = fminf(u.lo[2], slo.z);
+            u.hi[0] = fmaxf(u.hi[0], shi.x);
+            u.hi[1] = fmaxf(u.hi[1], shi.y);
+            u.hi[2] = fmaxf(u.hi[2], shi.z);
+            if (kCost)
+                u.cost = node_cost(col, u.r - u.l + 1, u.lo[0], u.lo[1], u.lo[2], u.hi[0], u.hi[1], u.hi[2],
+                                   goes_left ? own : scost, goes_left ? scost : own);
+            fresh = true;
         }
+    }
+    __syncthreads();
+    // first arrivals whose sibling never came go to the next level, with their
+    // slots cleared for it
+    const uint32_t np = min(s_npend, (uint32_t)kPendCap);
+    for (uint32_t j = threadIdx.x; j < np; j += kFitThreads) {
+        const int32_t g = s_pend[j];
+        const int32_t ex = out.slot[g];
+        if (ex >= 0) frontier_push(child_at(g, ex), &s_fcount, s_front, err);
+        out.slot[g] = kSlotEmpty;
     }
     __syncthreads();
     const uint32_t fc = min(s_fcount, (uint32_t)kFrontierCap);
@@ -552,31 +693,34 @@ hipError_t launch_gather64(const Workspace &w, int32_t n, const double *pos64, d
 namespace {
 
 template <bool kCost>
-void launch_fit_t(const Workspace &w, int32_t n, const Collapse &col, hipStream_t s) {
+void launch_tree_t(const Workspace &w, int32_t n, const TreeSource &src, int32_t kept_leaf, const Collapse &col,
+                   hipStream_t s) {
+    const TreeOut out{w.sorted, w.left, w.right, w.rf, w.rl, w.parent, w.leaf_parent, w.box_lo, w.box_hi, w.kept,
+                      w.cost, reinterpret_cast<int32_t *>(w.visit), reinterpret_cast<int32_t *>(w.keys2), kept_leaf};
     int32_t nchunks = fit_chunks0(n);
-    hipLaunchKernelGGL(k_fit_local<kCost>, dim3(nchunks), dim3(kFitThreads), 0, s, w.sorted, w.left, w.right, w.rf,
-                       w.rl, w.parent, w.leaf_parent, n, w.box_lo, w.box_hi, w.front[0], w.fcount[0], w.err, col,
-                       w.cost);
+    hipLaunchKernelGGL(k_tree_local<kCost>, dim3(nchunks), dim3(kFitThreads), 0, s, w.keys, w.vals, n, src, out,
+                       w.front[0], w.fcount[0], w.err, col);
     int64_t chunk = kFitChunk;
     int which = 0;
     while (chunk < n) {
         const int32_t nprev = nchunks;
         chunk *= kFitFanout;
         nchunks = (int32_t)((n + chunk - 1) / chunk);
-        hipLaunchKernelGGL(k_fit_level<kCost>, dim3(nchunks), dim3(kFitThreads), 0, s, w.sorted, w.left, w.right,
-                           w.rf, w.rl, w.parent, w.leaf_parent, chunk, nprev, w.front[which], w.fcount[which],
-                           w.visit, w.box_lo, w.box_hi, w.front[which ^ 1], w.fcount[which ^ 1], w.err, col, w.cost);
+        hipLaunchKernelGGL(k_tree_level<kCost>, dim3(nchunks), dim3(kFitThreads), 0, s, n, chunk, nprev,
+                           w.front[which], w.fcount[which], out, w.front[which ^ 1], w.fcount[which ^ 1], w.err, col);
         which ^= 1;
     }
 }
 
 }  // namespace
 
-hipError_t launch_fit(const Workspace &w, int32_t n, const Collapse &col, hipStream_t s) {
+hipError_t launch_tree(const Workspace &w, int32_t n, const TreeSource &src, int32_t kept_leaf, const Collapse &col,
+                       hipStream_t s) {
+    if (n <= 0) return hipSuccess;
     if (col.kVball > 0.0f)
-        launch_fit_t<true>(w, n, col, s);
+        launch_tree_t<true>(w, n, src, kept_leaf, col, s);
     else
-        launch_fit_t<false>(w, n, col, s);
+        launch_tree_t<false>(w, n, src, kept_leaf, col, s);
     return hipGetLastError();
 }
 
@@ -684,12 +828,7 @@ hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d
     if (ntypes > 1) hipLaunchKernelGGL(k_type_count, dim3(1), dim3(64), 0, s, w.keys, n, w.type_count);
     if (n > 0) {
         // (with the cost model, which nodes keep a record is known only after the fit)
-        hipLaunchKernelGGL(k_karras, grid_for(n), dim3(kBuildThreads), 0, s, w.keys, n, ntypes, w.type_count,
-                           by_cost ? INT32_MAX : leaf_size, d_pos, w.vals, w.sorted, w.left, w.right, w.rf, w.rl,
-                           w.parent, w.leaf_parent, w.visit, w.kept);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        e = launch_fit(w, n, col, s);
+        e = launch_tree(w, n, TreeSource{d_pos, nullptr, nullptr, 0}, by_cost ? INT32_MAX : leaf_size, col, s);
         if (e != hipSuccess) return e;
         if (by_cost)
             hipLaunchKernelGGL(k_kept_collapse, grid_for(n), dim3(kBuildThreads), 0, s, n, ntypes, w.keys,

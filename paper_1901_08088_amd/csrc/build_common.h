@@ -55,75 +55,6 @@ __device__ __forceinline__ int32_t run_ref(int32_t first, int32_t count) {
     return ~((first << kRunCountBits) | (count - 1));
 }
 
-// Sorted keys as the radix-tree construction reads them: positions near the
-// workgroup's own come from a copy staged in LDS (the searches of most nodes
-// stay within a few hundred positions), the others from global memory.
-struct StagedKeys {
-    const uint32_t *__restrict__ keys;
-    const uint32_t *lds;  // keys[lo, lo + len) (entries outside the segment unused)
-    int32_t lo, len;
-    __device__ __forceinline__ uint32_t operator()(int32_t j) const {
-        const uint32_t o = (uint32_t)(j - lo);
-        return o < (uint32_t)len ? lds[o] : keys[j];
-    }
-};
-
-// Stages keys[b0 - kBuildThreads, b0 + 2 kBuildThreads) of [s, e) into `lds`
-// (3 kBuildThreads entries).  Contains a barrier: every thread must call it.
-__device__ __forceinline__ StagedKeys stage_keys(const uint32_t *__restrict__ keys, uint32_t *lds, int32_t b0,
-                                                 int32_t s, int32_t e) {
-    const int32_t lo = b0 - kBuildThreads;
-    for (int32_t t = (int32_t)threadIdx.x; t < 3 * kBuildThreads; t += kBuildThreads) {
-        const int32_t j = lo + t;
-        lds[t] = (j >= s && j < e) ? keys[j] : 0u;
-    }
-    __syncthreads();
-    return StagedKeys{keys, lds, lo, 3 * kBuildThreads};
-}
-
-// Common-prefix length of the augmented keys (key << 32 | position); -1
-// outside the segment.  Equal keys are told apart by position (Karras's rule).
-template <class K>
-__device__ __forceinline__ int delta(const K &key, int32_t i, int32_t j, Segment g) {
-    if (j < g.s || j >= g.e) return -1;
-    const uint32_t a = key(i), b = key(j);
-    if (a != b) return __clz(a ^ b);
-    return 32 + __clz((uint32_t)(i ^ j));
-}
-
-struct KarrasNode {
-    int32_t left, right, f, l, gamma;
-};
-
-// Karras's parallel construction for internal node i of segment g (i < g.e - 1):
-// direction, far end and split by exponential then binary search on the
-// common-prefix length.  Children are internal ids or leaves as ~position.
-template <class K>
-__device__ __forceinline__ KarrasNode karras_node(const K &keys, int32_t i, Segment g) {
-    const int d = (delta(keys, i, i + 1, g) - delta(keys, i, i - 1, g)) > 0 ? 1 : -1;
-    const int dmin = delta(keys, i, i - d, g);
-    int32_t lmax = 2;
-    while (delta(keys, i, i + lmax * d, g) > dmin) lmax <<= 1;
-    int32_t l = 0;
-    for (int32_t t = lmax >> 1; t >= 1; t >>= 1)
-        if (delta(keys, i, i + (l + t) * d, g) > dmin) l += t;
-    const int32_t j = i + l * d;
-    const int dnode = delta(keys, i, j, g);
-    int32_t s = 0;
-    int32_t t = l;
-    do {
-        t = (t + 1) >> 1;
-        if (delta(keys, i, i + (s + t) * d, g) > dnode) s += t;
-    } while (t > 1);
-    KarrasNode r;
-    r.gamma = i + s * d + (d < 0 ? -1 : 0);
-    r.f = i < j ? i : j;
-    r.l = i < j ? j : i;
-    r.left = (r.f == r.gamma) ? ~r.gamma : r.gamma;
-    r.right = (r.l == r.gamma + 1) ? ~(r.gamma + 1) : r.gamma + 1;
-    return r;
-}
-
 __device__ __forceinline__ uint32_t quantize_lo(float v, float root, double h, uint32_t qmax) {
     double q = floor(((double)v - (double)root) / h);
     if (!(q >= 0.0)) q = 0.0;

@@ -50,13 +50,14 @@ struct Workspace {
     int32_t tiles = 0;        // radix-sort tiles for cap
     void *base = nullptr;     // single hipMalloc allocation
     size_t bytes = 0;
-    uint32_t *keys = nullptr, *vals = nullptr, *keys2 = nullptr, *vals2 = nullptr;
+    uint32_t *keys = nullptr, *vals = nullptr;
+    uint32_t *keys2 = nullptr, *vals2 = nullptr;  // sort ping-pong; keys2 then holds the tree build's exchange slots
     uint32_t *hist = nullptr;       // [256][tiles]
     uint32_t *digit_total = nullptr;// [256]
     float4 *sorted = nullptr;       // [cap + kSortedPad]
     int32_t *left = nullptr, *right = nullptr, *rf = nullptr, *rl = nullptr;
     int32_t *parent = nullptr, *leaf_parent = nullptr;
-    uint32_t *visit = nullptr;      // fit visit counters; with the cost model, then kept flags
+    uint32_t *visit = nullptr;      // split weights during the tree build; with the cost model, then kept flags
     float *cost = nullptr;          // subtree collapse: volume-weighted cost per internal node (negative: a run)
     float4 *box_lo = nullptr, *box_hi = nullptr;
     uint32_t *kept = nullptr;       // [cap + 1]: kept-node counts, scanned in place
@@ -184,7 +185,20 @@ hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, ui
                              hipStream_t s);
 hipError_t launch_exclusive_scan(uint32_t *data, int32_t len, uint32_t *partials, hipStream_t s);
 struct Collapse;
-hipError_t launch_fit(const Workspace &w, int32_t n, const Collapse &col, hipStream_t s);
+// Where the tree build takes its particles and tree boundaries from: a single
+// system (pos: positions [n][3] in input order; the sort's values are input
+// indices) or a batch (sysb and sys_off: system s owns sorted positions
+// [sys_off[s], sys_off[s + 1]); the sort's values are concatenated indices).
+struct TreeSource {
+    const float *pos;
+    const SysBuild *sysb;
+    const int32_t *sys_off;
+    int32_t nsys;
+};
+// Radix tree, Z-ordered particles, node boxes (and costs) and kept-node counts
+// (nodes longer than kept_leaf) from the sorted keys and values.
+hipError_t launch_tree(const Workspace &w, int32_t n, const TreeSource &src, int32_t kept_leaf, const Collapse &col,
+                       hipStream_t s);
 int32_t fit_chunks0(int32_t cap);
 // Stable sort of each segment [seg_off[s], seg_off[s+1]) of (keys, vals) on
 // its own; tile_first[s] = sum over earlier segments of seg_radix_tiles(size),
