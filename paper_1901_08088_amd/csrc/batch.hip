@@ -112,7 +112,6 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_emit(const int32_t *__restr
                                                           const uint32_t *__restrict__ type_count,
                                                           const float4 *__restrict__ sorted,
                                                           const int32_t *__restrict__ left,
-                                                          const int32_t *__restrict__ right,
                                                           const int32_t *__restrict__ rf, const int32_t *__restrict__ rl,
                                                           const int32_t *__restrict__ parent,
                                                           const float4 *__restrict__ box_lo,
@@ -149,8 +148,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_emit(const int32_t *__restr
     if (threadIdx.x >= s_count) return;
     const int32_t k = s_ids[threadIdx.x];
     const TreeMeta &m = meta[it.sys * QBVH_MAX_TYPES + (keys[k] >> 30)];
-    emit_record(k, rf[k], rl[k], m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, nullptr, qbits,
-                records, ropes);
+    emit_record(k, rf[k], rl[k], m, sorted, left, parent, box_lo, box_hi, P, leaf_size, nullptr, qbits, records,
+                ropes);
 }
 
 }  // namespace
@@ -179,7 +178,7 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t s) {
                        w.sorted, w.box_lo, w.box_hi, w.kept, b.qbits, b.leaf_size, b.meta);
     if (b.total > 0)
         hipLaunchKernelGGL(k_b_emit, dim3((unsigned)b.blocks), dim3(kBuildThreads), 0, s, b.blk_first, b.nsys, b.sysb,
-                           w.keys, b.type_count, w.sorted, w.left, w.right, w.rf, w.rl, w.parent, w.box_lo,
+                           w.keys, b.type_count, w.sorted, w.left, w.rf, w.rl, w.parent, w.box_lo,
                            w.box_hi, w.kept, b.meta, b.leaf_size, b.qbits, w.records, w.ropes);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

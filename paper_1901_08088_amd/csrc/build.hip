@@ -602,7 +602,6 @@ __global__ __launch_bounds__(kBuildThreads) void k_emit(int32_t n, int32_t ntype
                                                         const uint32_t *__restrict__ type_count,
                                                         const float4 *__restrict__ sorted,
                                                         const int32_t *__restrict__ left,
-                                                        const int32_t *__restrict__ right,
                                                         const int32_t *__restrict__ rf, const int32_t *__restrict__ rl,
                                                         const int32_t *__restrict__ parent,
                                                         const float4 *__restrict__ box_lo,
@@ -641,8 +640,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_emit(int32_t n, int32_t ntype
     for (uint32_t e = threadIdx.x; e < count; e += kBuildThreads) {
         const int32_t i = s_ids[e];
         const TreeMeta &m = meta[ntypes == 1 ? 0 : (keys[i] >> 30)];
-        emit_record(i, rf[i], rl[i], m, sorted, left, right, rf, rl, parent, box_lo, box_hi, P, leaf_size, kept_flag,
-                    qbits, records, ropes);
+        emit_record(i, rf[i], rl[i], m, sorted, left, parent, box_lo, box_hi, P, leaf_size, kept_flag, qbits, records,
+                    ropes);
     }
 }
 
@@ -843,7 +842,7 @@ hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d
     if (n > 0)
         hipLaunchKernelGGL(k_emit, grid_for((n + kEmitItems - 1) / kEmitItems), dim3(kBuildThreads), 0, s, n, ntypes,
                            w.keys, w.type_count,
-                           w.sorted, w.left, w.right, w.rf, w.rl, w.parent, w.box_lo, w.box_hi, w.kept, w.meta,
+                           w.sorted, w.left, w.rf, w.rl, w.parent, w.box_lo, w.box_hi, w.kept, w.meta,
                            leaf_size, by_cost ? w.visit : nullptr, qbits, w.records, w.ropes);
     return hipGetLastError();
 }

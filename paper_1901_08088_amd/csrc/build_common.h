@@ -145,56 +145,52 @@ __device__ __forceinline__ TreeMeta tree_meta(const float lo[3], const float hi[
 // longer than leaf_size, or with the cost model, kept_flag[i] set): both
 // child boxes quantized against the tree's root box, both child references,
 // written at its preorder position, plus its rope.  A child is a record when
-// it is kept itself, otherwise a particle run.
+// it is kept itself, otherwise a particle run.  The children are the left
+// [f, g] and the right [g + 1, l] around the node's split g (ids g and g + 1
+// when internal), so their ranges need no loads.
+//
+// Preorder position: the kept nodes starting before f (P[f]), then those
+// starting at f that contain node i (they nest along a left spine and come
+// before it in preorder; all of them are kept, being longer than i).  A node
+// starting at f is a left child exactly when its id is not f (a left child
+// takes the end of its range as id; a right child or a root takes f), so the
+// ancestors starting at f are found by following parent links from i while
+// the id differs from f: one load per step.
 __device__ __forceinline__ void emit_record(int32_t i, int32_t f, int32_t l, const TreeMeta &m,
                                             const float4 *__restrict__ sorted, const int32_t *__restrict__ left,
-                                            const int32_t *__restrict__ right, const int32_t *__restrict__ rf,
-                                            const int32_t *__restrict__ rl, const int32_t *__restrict__ parent,
+                                            const int32_t *__restrict__ parent,
                                             const float4 *__restrict__ box_lo, const float4 *__restrict__ box_hi,
                                             const uint32_t *__restrict__ P, int32_t leaf_size,
                                             const uint32_t *__restrict__ kept_flag, int32_t qbits,
                                             uint4 *__restrict__ records, int32_t *__restrict__ ropes) {
-    // Everything that does not depend on the preorder rank is loaded first,
-    // so that those loads overlap the rank climb (a chain of dependent loads).
-    // A leaf child's box is its particle; its range loads read node i's own
-    // entries instead (in bounds, already cached) and are not used.
-    const int32_t ch[2] = {left[i], right[i]};
+    const int32_t lc = left[i];
+    const int32_t g = lc >= 0 ? lc : ~lc;
+    const int32_t cf[2] = {f, g + 1}, cl[2] = {g, l};
+    // A leaf child's box is its particle.
     float4 lo[2], hi[2];
-    int32_t cf[2], cl[2];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-        const int32_t c = ch[side];
-        const bool leaf = c < 0;
-        const int32_t k = leaf ? ~c : c;
+        const bool leaf = cf[side] == cl[side];
+        const int32_t k = side == 0 ? g : g + 1;
         lo[side] = *(leaf ? sorted + k : box_lo + k);
         hi[side] = *(leaf ? sorted + k : box_hi + k);
-        const int32_t r = leaf ? i : c;
-        const int32_t rfv = rf[r], rlv = rl[r];
-        cf[side] = leaf ? k : rfv;
-        cl[side] = leaf ? k : rlv;
     }
-    const uint32_t right_rec = P[cf[1]];
+    const uint32_t right_rec = P[g + 1];
     const int32_t rope = (int32_t)P[l + 1];
-    const int32_t first_rec = (int32_t)P[f];
+    const uint32_t first_rec = P[f];
+    // (issued after the loads above, so those overlap the chain)
+    int32_t rank = 0;
+    for (int32_t u = i; u != f && rank < kMaxDepth; ++rank) u = parent[u];
+    const int32_t at = (int32_t)first_rec + rank;
     const float root[3] = {m.lo[0], m.lo[1], m.lo[2]};
     const double h = m.h;
-    // preorder position: kept nodes starting before f, plus the ancestors
-    // that start at f (the chain of nodes of which i is the left child)
-    int32_t rank = 0;
-    int32_t u = i;
-    for (int step = 0; step < kMaxDepth; ++step) {
-        const int32_t pp = parent[u];
-        if (pp < 0 || left[pp] != u) break;
-        ++rank;
-        u = pp;
-    }
-    const int32_t at = first_rec + rank;
     const uint32_t qmax = (1u << qbits) - 1u;
     uint32_t w[8];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const int32_t count = cl[side] - cf[side] + 1;
-        const bool record = ch[side] >= 0 && (kept_flag ? kept_flag[ch[side]] != 0u : count > leaf_size);
+        const int32_t id = side == 0 ? g : g + 1;
+        const bool record = count > 1 && (kept_flag ? kept_flag[id] != 0u : count > leaf_size);
         int32_t ref;
         if (record)
             ref = side == 0 ? at + 1 : (int32_t)right_rec;
