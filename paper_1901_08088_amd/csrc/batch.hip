@@ -47,21 +47,19 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_init(int32_t nsys, uint32_t
 
 __global__ __launch_bounds__(kBuildThreads) void k_b_morton(const int32_t *__restrict__ blk_first, int32_t nsys,
                                                             const SysBuild *__restrict__ sysb, int32_t total,
-                                                            uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                            uint32_t *__restrict__ keys,
                                                             uint32_t *__restrict__ kept) {
     const Item it = item_of(blk_first, nsys);
     const SysBuild &y = sysb[it.sys];
     if (blockIdx.x == 0 && threadIdx.x == 0) kept[total] = 0;
     if (it.local < y.n) {
         const int32_t k = y.off + it.local;
-        kept[k] = 0;
         const float x = y.pos[3 * (int64_t)it.local + 0];
         const float yy = y.pos[3 * (int64_t)it.local + 1];
         const float z = y.pos[3 * (int64_t)it.local + 2];
         int32_t t = y.type ? y.type[it.local] : 0;
         t = t < 0 ? 0 : (t >= y.ntypes ? y.ntypes - 1 : t);
         keys[k] = morton_key(x, yy, z, y.scale[0], y.scale[1], y.scale[2], t);
-        vals[k] = (uint32_t)k;
     }
 }
 
@@ -161,7 +159,7 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t s) {
                        0, s, b.nsys, b.type_count, b.trav, w.err);
     if (b.blocks > 0)
         hipLaunchKernelGGL(k_b_morton, dim3((unsigned)b.blocks), dim3(kBuildThreads), 0, s, b.blk_first, b.nsys,
-                           b.sysb, b.total, w.keys, w.vals, w.kept);
+                           b.sysb, b.total, w.keys, w.kept);
     hipError_t e = launch_radix_sort_segmented(w.keys, w.vals, w.keys2, w.vals2, b.hist, b.scan_part, b.total,
                                                b.tiles, b.tile_first, b.sys_off, b.nsys, s);
     if (e != hipSuccess) return e;

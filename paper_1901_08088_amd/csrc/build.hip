@@ -42,10 +42,12 @@ __global__ __launch_bounds__(kBuildThreads) void k_morton(const float *__restric
                                                           const int32_t *__restrict__ type, int32_t n,
                                                           int32_t ntypes, float Lx, float Ly, float Lz,
                                                           double sx, double sy, double sz, int32_t validate,
-                                                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                          uint32_t *__restrict__ keys,
                                                           uint32_t *__restrict__ kept, int32_t *err) {
     const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
-    if (k <= n) kept[k] = 0;
+    // the kept counts of positions < n are written by the tree build; the
+    // scan's extra entry is cleared here
+    if (k == n) kept[n] = 0;
     if (k < n) {
         const float x = pos[3 * (int64_t)k + 0];
         const float y = pos[3 * (int64_t)k + 1];
@@ -58,7 +60,6 @@ __global__ __launch_bounds__(kBuildThreads) void k_morton(const float *__restric
         }
         t = t < 0 ? 0 : (t >= ntypes ? ntypes - 1 : t);
         keys[k] = morton_key(x, y, z, sx, sy, sz, t);
-        vals[k] = (uint32_t)k;
     }
 }
 
@@ -821,7 +822,7 @@ hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d
     const double sy = 1023.0 / (double)box[1];
     const double sz = 1023.0 / (double)box[2];
     hipLaunchKernelGGL(k_morton, grid_for((int64_t)n + 1), dim3(kBuildThreads), 0, s, d_pos, d_type, n, ntypes,
-                       box[0], box[1], box[2], sx, sy, sz, validate, w.keys, w.vals, w.kept, w.err);
+                       box[0], box[1], box[2], sx, sy, sz, validate, w.keys, w.kept, w.err);
     hipError_t e = launch_radix_sort(w.keys, w.vals, w.keys2, w.vals2, w.hist, w.digit_total, n, w.tiles, s);
     if (e != hipSuccess) return e;
     if (ntypes > 1) hipLaunchKernelGGL(k_type_count, dim3(1), dim3(64), 0, s, w.keys, n, w.type_count);

@@ -47,7 +47,7 @@ struct GridGeom {
 };
 
 __global__ __launch_bounds__(kGridThreads) void k_cell_key(const float *__restrict__ pos, int32_t n, GridGeom g,
-                                                           uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+                                                           uint32_t *__restrict__ keys) {
     const int32_t i = blockIdx.x * kGridThreads + threadIdx.x;
     if (i >= n) return;
     int32_t c[3];
@@ -59,7 +59,6 @@ __global__ __launch_bounds__(kGridThreads) void k_cell_key(const float *__restri
         c[d] = (int32_t)v;
     }
     keys[i] = (uint32_t)((c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0]);
-    vals[i] = (uint32_t)i;
 }
 
 __global__ __launch_bounds__(kGridThreads) void k_cell_clear(int32_t *__restrict__ start, int32_t *__restrict__ end,
@@ -288,8 +287,7 @@ int nlist_build_grid(qgrid_t **grid, const float *d_pos, int32_t n, const float 
 
     hipLaunchKernelGGL(qbi::k_grid_clear_flag, dim3(1), dim3(64), 0, s, d_overflow);
     if (n > 0) {
-        hipLaunchKernelGGL(qbi::k_cell_key, qbi::blocks_for(n), dim3(qbi::kGridThreads), 0, s, d_pos, n, g, G->keys,
-                           G->vals);
+        hipLaunchKernelGGL(qbi::k_cell_key, qbi::blocks_for(n), dim3(qbi::kGridThreads), 0, s, d_pos, n, g, G->keys);
         hipError_t e = qbi::launch_radix_sort(G->keys, G->vals, G->keys2, G->vals2, G->hist, G->digit_total, n,
                                               qbi::radix_tiles(n), s);
         if (e != hipSuccess) return qbi::hip_fail(e);

@@ -180,6 +180,8 @@ hipError_t launch_gather64(const Workspace &w, int32_t n, const double *pos64, d
 hipError_t launch_qpoint(const Workspace &w, int32_t n, int32_t ntypes, int32_t qbits, double lmax, hipStream_t s);
 hipError_t launch_traverse_batch(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t s);
+// Stable sort of keys[0, n); vals receives each sorted key's input position
+// (the caller writes only the keys).
 hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
                              uint32_t *hist, uint32_t *digit_total, int32_t n, int32_t tiles,
                              hipStream_t s);
@@ -200,8 +202,8 @@ struct TreeSource {
 hipError_t launch_tree(const Workspace &w, int32_t n, const TreeSource &src, int32_t kept_leaf, const Collapse &col,
                        hipStream_t s);
 int32_t fit_chunks0(int32_t cap);
-// Stable sort of each segment [seg_off[s], seg_off[s+1]) of (keys, vals) on
-// its own; tile_first[s] = sum over earlier segments of seg_radix_tiles(size),
+// Stable sort of each segment [seg_off[s], seg_off[s+1]) of keys on its own,
+// vals receiving each sorted key's position in the concatenation; tile_first[s] = sum over earlier segments of seg_radix_tiles(size),
 // tiles = tile_first[nseg]; hist holds 256 * tiles counters, scan_part
 // scan_blocks(256 * tiles) + 1.
 hipError_t launch_radix_sort_segmented(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
