@@ -8,7 +8,9 @@
  *   - Section 2.1: particles get 30-bit Morton codes (2^10 - 1 bins per axis
  *     of the periodic box), are sorted along the Z-order curve, Karras's
  *     radix tree is emitted over the sorted codes and axis-aligned boxes are
- *     fit bottom-up, giving N - 1 internal nodes with two children each;
+ *     fit bottom-up, giving N - 1 internal nodes with two children each
+ *     (this library finds the same tree, with Karras's node ids, bottom-up in
+ *     the same climb as the fit);
  *   - Section 2.2: node bounds are snapped outward to an integer grid over
  *     the root-node box and packed with a skip rope (the paper's node is 16
  *     bytes; this library stores both children of a node in one 32-byte
