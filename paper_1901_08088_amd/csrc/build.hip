@@ -741,7 +741,7 @@ size_t workspace_bytes(int32_t cap) {
     b += al(256 * tiles * 4) + al(256 * 4);   // histograms
     b += al((c + kSortedPad) * 16);           // sorted (+ padding read by whole-run loads)
     b += 6 * al(c * 4);                       // left right rf rl parent leaf_parent
-    b += al(c * 4);                           // visit (fit counters, then kept flags)
+    b += al(c * 4);                           // visit (split weights, then kept flags)
     b += al(c * 4);                           // cost (subtree collapse)
     b += 2 * al(c * 16);                      // boxes
     b += al((c + 1) * 4) + al(sb * 4);        // kept + scan partials
@@ -749,7 +749,7 @@ size_t workspace_bytes(int32_t cap) {
     b += al((c + kSortedPad) * 16);           // cell boxes (paper-mode lists)
     b += al(QBVH_MAX_TYPES * sizeof(TreeMeta)) + al(QBVH_MAX_TYPES * 4) + al(4);
     const size_t nf = (size_t)fit_chunks0((int32_t)c);
-    b += 2 * (al(nf * kFrontierCap * 4) + al(nf * 4));  // fit frontiers (ping-pong)
+    b += 2 * (al(nf * kFrontierCap * 4) + al(nf * 4));  // tree-build frontiers (ping-pong)
     return b;
 }
 
