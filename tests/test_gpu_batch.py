@@ -77,6 +77,23 @@ def test_batch_matches_oracle_and_plain(opts):
     _check_all(cfgs, batch_results(systems, cfgs), 256, _plain_counts(cfgs, 256))
 
 
+@pytest.mark.parametrize("sizes", [(1,), (1, 0), (0, 2), (2, 1)])
+def test_batch_tiny_totals(sizes):
+    """Batches whose concatenation holds one or two particles: the sort then
+    runs on an array of one or two elements and must still give every
+    position its value."""
+    require_gpu()
+    cfgs = []
+    for k, n in enumerate(sizes):
+        pos = np.array([[1.0, 2.0, 3.0], [1.5, 2.5, 3.0]], np.float32)[:n]
+        cfgs.append(W.Config(pos=pos.reshape(-1, 3), box=np.full(3, 8.0, np.float32), rcut=np.array([[2.0]], np.float32),
+                             skin=0.3, name=f"tiny {k} N={n}"))
+    systems = batch_buffers(cfgs, max_nbr=8)
+    print(f"[batch] tiny totals {sizes}", flush=True)
+    Q.nlist_build_many(systems, dict(leaf_size=4))
+    _check_all(cfgs, batch_results(systems, cfgs), 8)
+
+
 def test_batch_overflow_and_scalar_rows():
     """max_nbr = 37: rows take scalar stores, many rows overflow."""
     require_gpu()
