@@ -24,7 +24,6 @@ namespace qbi {
 namespace {
 
 constexpr int32_t kBuildBlock = 256;  // work-items per build workgroup (kBuildThreads)
-constexpr int32_t kTileItems = 4096;  // keys per radix-sort tile
 constexpr int kTrialsPerCandidate = 2;
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -340,7 +339,7 @@ void fill_table(const BatchCtx &c, int32_t nsys, const qbvh_system_t *sys, const
         ta[s] = a;
         off += y.n;
         b += div_up(y.n, kBuildBlock);
-        t += div_up(y.n, kTileItems);
+        t += seg_radix_tiles(y.n);
         tb += (int32_t)trav_blocks(y.n, y.ntypes, cfg.block, qpw);
     }
     sys_off[nsys] = off;
@@ -444,7 +443,7 @@ int run_many(int32_t nsys, const qbvh_system_t *sys, const qbvh_batch_opts_t *op
         a.max_nbr = y.max_nbr;
         if (y.n > 0) vec4 = vec4 && y.max_nbr > 0 && (y.max_nbr % 4) == 0 && (((uintptr_t)y.d_nbr) & 15u) == 0;
         total += y.n;
-        tiles += div_up(y.n, kTileItems);
+        tiles += seg_radix_tiles(y.n);
         blocks += div_up(y.n, kBuildBlock);
         key.push_back(y.n);
         key.push_back(y.ntypes);
