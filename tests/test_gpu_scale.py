@@ -108,3 +108,33 @@ def test_every_row_at_1m(kind):
     okey = (rows << 32) | cols.astype(np.int64)
     assert np.array_equal(gkey, okey), f"{int(np.count_nonzero(gkey != okey))} entries differ"
     print(f"[scale] every row {kind} N={n}: {gkey.size} entries equal", flush=True)
+
+
+@pytest.mark.parametrize("kind,radius", [("lj", 3.4), ("wca", 1.52)])
+def test_cost_collapse_at_1m(kind, radius):
+    # the cost model's build (costs carried up every level of the climb, then
+    # the kept nodes marked) at a size with two upper levels: every count and
+    # sampled rows against the oracle
+    torch = require_gpu()
+    cfg = W.lj_fluid(1_000_000) if kind == "lj" else W.wca_fluid(1_000_000)
+    n = cfg.n
+    opts = dict(BENCH_OPTS, collapse_radius=radius)
+    print(f"[scale] cost collapse {kind} N={n} R={radius}", flush=True)
+    pos = torch.from_numpy(cfg.pos).cuda()
+    tree = Q.qbvh_build(pos, None, cfg.box, 1, opts)
+    max_nbr = 256
+    nbr = torch.empty((n, max_nbr), dtype=torch.int32, device="cuda")
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    ovf = torch.empty(1, dtype=torch.int32, device="cuda")
+    Q.nlist_build(tree, cfg.rcut, cfg.skin, max_nbr, nbr, cnt, ovf)
+    torch.cuda.synchronize()
+    gcnt = cnt.cpu().numpy().astype(np.int64)
+    ocnt = oracle.neighbor_counts(cfg.pos, cfg.box, cfg.rcut, cfg.skin)
+    assert np.array_equal(gcnt, ocnt), f"{int(np.count_nonzero(gcnt != ocnt))} count mismatches"
+    assert int(ovf.item()) == int((ocnt > max_nbr).any())
+    sample = np.sort(np.random.default_rng(n + 17).choice(n, 2000, replace=False))
+    rows = nbr[torch.from_numpy(sample).cuda()].cpu().numpy()
+    rp, cols = oracle.neighbor_lists(cfg.pos, cfg.box, cfg.rcut, cfg.skin, queries=sample)
+    for q, i in enumerate(sample):
+        assert sorted(rows[q, :gcnt[i]].tolist()) == cols[rp[q]:rp[q + 1]].tolist(), i
+    Q.qbvh_free(tree)
