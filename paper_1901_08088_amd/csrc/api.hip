@@ -305,8 +305,7 @@ int qbvh_build_f64(qbvh_t **tree, const double *d_pos, const int32_t *d_type, in
                                       t->err64, s);
     if (e == hipSuccess)
         e = qbi::launch_build(t->ws, t->pos32, ntypes > 1 ? d_type : nullptr, n, ntypes, t->box, o.leaf_size,
-                              o.qbits, o.collapse_radius, 0, s);
-    if (e == hipSuccess) e = qbi::launch_gather64(t->ws, n, d_pos, t->sorted64, s);
+                              o.qbits, o.collapse_radius, 0, s, d_pos, t->sorted64);
     if (e != hipSuccess) return hip_fail(e);
     return o.validate ? check_valid(t->err64, s) : QBVH_OK;
 }

@@ -166,7 +166,7 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t s) {
     hipLaunchKernelGGL(k_b_type_count, dim3((unsigned)((ninit + kBuildThreads - 1) / kBuildThreads)),
                        dim3(kBuildThreads), 0, s, b.nsys, b.sysb, w.keys, b.type_count);
     if (b.total > 0) {
-        e = launch_tree(w, b.total, TreeSource{nullptr, b.sysb, b.sys_off, b.nsys}, b.leaf_size,
+        e = launch_tree(w, b.total, TreeSource{nullptr, b.sysb, b.sys_off, b.nsys, nullptr, nullptr}, b.leaf_size,
                         Collapse{0.f, 0.f, 0.f, b.leaf_size}, s);
         if (e != hipSuccess) return e;
     }

@@ -97,21 +97,6 @@ __global__ __launch_bounds__(kBuildThreads) void k_to_f32(const double *__restri
     pos32[3 * (int64_t)i + 2] = (float)z;
 }
 
-// fp64 particle data, after the build: the fp64 position of every sorted
-// particle (its input index is the inverted w word of the fp32 copy).
-__global__ __launch_bounds__(kBuildThreads) void k_gather64(const float4 *__restrict__ sorted, int32_t n,
-                                                            const double *__restrict__ pos64,
-                                                            double *__restrict__ sorted64) {
-    const int32_t k = blockIdx.x * kBuildThreads + threadIdx.x;
-    if (k >= n) return;
-    const int64_t i = ~__float_as_int(sorted[k].w);
-    double *o = sorted64 + 4 * (int64_t)k;
-    o[0] = pos64[3 * i + 0];
-    o[1] = pos64[3 * i + 1];
-    o[2] = pos64[3 * i + 2];
-    o[3] = 0.0;
-}
-
 // Radix tree and node boxes in one bottom-up pass (Section 2.1: the hierarchy
 // over the Z-ordered particles, its boxes fit from the leaves up).  The tree
 // is the binary radix tree of the augmented keys (key, position): the split
@@ -259,7 +244,23 @@ __global__ __launch_bounds__(kFitThreads) void k_tree_local(const uint32_t *__re
     const int32_t t = threadIdx.x;
     // the particle's loads go out first and complete while the keys are staged
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (t < m) p = gather_particle(src, vals, c0 + t);
+    if (t < m) {
+        if (src.pos64 != nullptr) {
+            // fp64 data: the particle rounded to fp32 for the tree (as the
+            // Morton codes were), its fp64 position kept in Z order as well
+            const uint32_t o = vals[c0 + t];
+            const double x = src.pos64[3 * (int64_t)o + 0], y = src.pos64[3 * (int64_t)o + 1],
+                         z = src.pos64[3 * (int64_t)o + 2];
+            p = make_float4((float)x, (float)y, (float)z, __int_as_float(~(int32_t)o));
+            double *q = src.sorted64 + 4 * (int64_t)(c0 + t);
+            q[0] = x;
+            q[1] = y;
+            q[2] = z;
+            q[3] = 0.0;
+        } else {
+            p = gather_particle(src, vals, c0 + t);
+        }
+    }
     for (int32_t j = t; j < m + 2; j += kFitThreads) {
         const int32_t k = c0 - 1 + j;
         s_keykept[j] = (k >= 0 && k < n) ? keys[k] : 0u;
@@ -684,12 +685,6 @@ hipError_t launch_to_f32(const double *pos64, const int32_t *type, int32_t n, in
     return hipGetLastError();
 }
 
-hipError_t launch_gather64(const Workspace &w, int32_t n, const double *pos64, double *sorted64, hipStream_t s) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_gather64, grid_for(n), dim3(kBuildThreads), 0, s, w.sorted, n, pos64, sorted64);
-    return hipGetLastError();
-}
-
 namespace {
 
 template <bool kCost>
@@ -814,7 +809,7 @@ Collapse collapse_model(float collapse_radius, int32_t leaf_size) {
 
 hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d_type, int32_t n, int32_t ntypes,
                         const float box[3], int32_t leaf_size, int32_t qbits, float collapse_radius, int32_t validate,
-                        hipStream_t s) {
+                        hipStream_t s, const double *pos64, double *sorted64) {
     const Collapse col = collapse_model(collapse_radius, leaf_size);
     const bool by_cost = col.kVball > 0.0f;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, w.type_count, w.err);
@@ -828,7 +823,8 @@ hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d
     if (ntypes > 1) hipLaunchKernelGGL(k_type_count, dim3(1), dim3(64), 0, s, w.keys, n, w.type_count);
     if (n > 0) {
         // (with the cost model, which nodes keep a record is known only after the fit)
-        e = launch_tree(w, n, TreeSource{d_pos, nullptr, nullptr, 0}, by_cost ? INT32_MAX : leaf_size, col, s);
+        e = launch_tree(w, n, TreeSource{d_pos, nullptr, nullptr, 0, pos64, sorted64}, by_cost ? INT32_MAX : leaf_size,
+                        col, s);
         if (e != hipSuccess) return e;
         if (by_cost)
             hipLaunchKernelGGL(k_kept_collapse, grid_for(n), dim3(kBuildThreads), 0, s, n, ntypes, w.keys,
