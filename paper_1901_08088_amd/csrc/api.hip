@@ -22,15 +22,13 @@ struct qbvh {
     qbvh_opts_t opts{};
     hipStream_t stream = nullptr;
     // fp64 particle data (qbvh_build_f64): the box in fp64 and, in one extra
-    // allocation for cap64 particles, the data rounded to fp32 (the build's
-    // input), the sorted fp64 positions (the exact decisions) and an error word
+    // allocation for cap64 particles, the sorted fp64 positions (the exact
+    // decisions)
     int32_t f64 = 0;
     double box64[3] = {0.0, 0.0, 0.0};
     void *mem64 = nullptr;
     int32_t cap64 = 0;
-    float *pos32 = nullptr;
     double *sorted64 = nullptr;
-    int32_t *err64 = nullptr;
 };
 
 namespace {
@@ -279,15 +277,12 @@ int qbvh_build_f64(qbvh_t **tree, const double *d_pos, const int32_t *d_type, in
             t->cap64 = 0;
         }
         const int32_t cap = n > 0 ? n : 1;
-        const size_t b32 = ((size_t)cap * 12 + 255) & ~(size_t)255;
         void *m = nullptr;
-        hipError_t e = hipMalloc(&m, b32 + (size_t)cap * 32 + 256);
+        hipError_t e = hipMalloc(&m, (size_t)cap * 32);
         if (e != hipSuccess) return hip_fail(e);
         t->mem64 = m;
         t->cap64 = cap;
-        t->pos32 = (float *)m;
-        t->sorted64 = (double *)((char *)m + b32);
-        t->err64 = (int32_t *)((char *)m + b32 + (size_t)cap * 32);
+        t->sorted64 = (double *)m;
     }
     t->n = n;
     t->ntypes = ntypes;
@@ -300,14 +295,11 @@ int qbvh_build_f64(qbvh_t **tree, const double *d_pos, const int32_t *d_type, in
     t->stream = s;
 
     // the build runs on the data rounded to fp32 (a point may round onto the
-    // box edge, which the Morton bins clamp); validation is done here in fp64
-    hipError_t e = qbi::launch_to_f32(d_pos, ntypes > 1 ? d_type : nullptr, n, ntypes, box, o.validate, t->pos32,
-                                      t->err64, s);
-    if (e == hipSuccess)
-        e = qbi::launch_build(t->ws, t->pos32, ntypes > 1 ? d_type : nullptr, n, ntypes, t->box, o.leaf_size,
-                              o.qbits, o.collapse_radius, 0, s, d_pos, t->sorted64);
+    // box edge, which the Morton bins clamp); validation is done in fp64
+    hipError_t e = qbi::launch_build(t->ws, nullptr, ntypes > 1 ? d_type : nullptr, n, ntypes, t->box, o.leaf_size,
+                                     o.qbits, o.collapse_radius, o.validate, s, d_pos, t->sorted64, box);
     if (e != hipSuccess) return hip_fail(e);
-    return o.validate ? check_valid(t->err64, s) : QBVH_OK;
+    return o.validate ? check_valid(t->ws.err, s) : QBVH_OK;
 }
 
 int nlist_build_ex(const qbvh_t *tree, const float *rcut, float skin, int32_t max_nbr, int32_t mode,

@@ -38,9 +38,14 @@ __global__ __launch_bounds__(kBuildThreads) void k_init(uint32_t *type_count, in
     if (threadIdx.x == 0) *err = 0;
 }
 
-__global__ __launch_bounds__(kBuildThreads) void k_morton(const float *__restrict__ pos,
+// Morton keys from fp32 or fp64 positions.  fp64 data: the bins are taken
+// from each coordinate rounded to nearest fp32 (what the tree is built on)
+// and the optional checks 0 <= x < L are made in fp64 against the fp64 box;
+// fp32 data: L is the fp32 box (compared exactly after promotion).
+template <class T>
+__global__ __launch_bounds__(kBuildThreads) void k_morton(const T *__restrict__ pos,
                                                           const int32_t *__restrict__ type, int32_t n,
-                                                          int32_t ntypes, float Lx, float Ly, float Lz,
+                                                          int32_t ntypes, double Lx, double Ly, double Lz,
                                                           double sx, double sy, double sz, int32_t validate,
                                                           uint32_t *__restrict__ keys,
                                                           uint32_t *__restrict__ kept, int32_t *err) {
@@ -49,17 +54,17 @@ __global__ __launch_bounds__(kBuildThreads) void k_morton(const float *__restric
     // scan's extra entry is cleared here
     if (k == n) kept[n] = 0;
     if (k < n) {
-        const float x = pos[3 * (int64_t)k + 0];
-        const float y = pos[3 * (int64_t)k + 1];
-        const float z = pos[3 * (int64_t)k + 2];
+        const T x = pos[3 * (int64_t)k + 0];
+        const T y = pos[3 * (int64_t)k + 1];
+        const T z = pos[3 * (int64_t)k + 2];
         int32_t t = type ? type[k] : 0;
         if (validate) {
-            bool ok = (x >= 0.0f && x < Lx) && (y >= 0.0f && y < Ly) && (z >= 0.0f && z < Lz) &&
-                      (t >= 0 && t < ntypes);
+            const bool ok = ((double)x >= 0.0 && (double)x < Lx) && ((double)y >= 0.0 && (double)y < Ly) &&
+                            ((double)z >= 0.0 && (double)z < Lz) && (t >= 0 && t < ntypes);
             if (!ok) atomicOr(err, 1);
         }
         t = t < 0 ? 0 : (t >= ntypes ? ntypes - 1 : t);
-        keys[k] = morton_key(x, y, z, sx, sy, sz, t);
+        keys[k] = morton_key((float)x, (float)y, (float)z, sx, sy, sz, t);
     }
 }
 
@@ -69,32 +74,6 @@ __global__ void k_type_count(const uint32_t *__restrict__ keys, int32_t n, uint3
     const uint32_t t = threadIdx.x;
     if (t < QBVH_MAX_TYPES)
         type_count[t] = (uint32_t)(type_start(keys, 0, n, t + 1) - type_start(keys, 0, n, t));
-}
-
-// fp64 particle data, before the build: each coordinate rounded to nearest
-// fp32 (the tree is built and walked on these; the exact decisions use the
-// fp64 values), with the fp64 checks 0 <= x < L and 0 <= type < ntypes when
-// `validate` is set (*err, cleared by k_clear_err before, is set on failure).
-__global__ void k_clear_err(int32_t *err) {
-    if (threadIdx.x == 0) *err = 0;
-}
-
-__global__ __launch_bounds__(kBuildThreads) void k_to_f32(const double *__restrict__ pos64,
-                                                          const int32_t *__restrict__ type, int32_t n,
-                                                          int32_t ntypes, double Lx, double Ly, double Lz,
-                                                          int32_t validate, float *__restrict__ pos32,
-                                                          int32_t *err) {
-    const int32_t i = blockIdx.x * kBuildThreads + threadIdx.x;
-    if (i >= n) return;
-    const double x = pos64[3 * (int64_t)i + 0], y = pos64[3 * (int64_t)i + 1], z = pos64[3 * (int64_t)i + 2];
-    if (validate) {
-        const int32_t t = type ? type[i] : 0;
-        const bool ok = (x >= 0.0 && x < Lx) && (y >= 0.0 && y < Ly) && (z >= 0.0 && z < Lz) && t >= 0 && t < ntypes;
-        if (!ok) atomicOr(err, 1);
-    }
-    pos32[3 * (int64_t)i + 0] = (float)x;
-    pos32[3 * (int64_t)i + 1] = (float)y;
-    pos32[3 * (int64_t)i + 2] = (float)z;
 }
 
 // Radix tree and node boxes in one bottom-up pass (Section 2.1: the hierarchy
@@ -676,15 +655,6 @@ inline dim3 grid_for(int64_t items) { return dim3((unsigned)((items + kBuildThre
 
 int32_t fit_chunks0(int32_t cap) { return (cap + kFitChunk - 1) / kFitChunk; }
 
-hipError_t launch_to_f32(const double *pos64, const int32_t *type, int32_t n, int32_t ntypes, const double box[3],
-                         int32_t validate, float *pos32, int32_t *err, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(64), 0, s, err);
-    if (n > 0)
-        hipLaunchKernelGGL(k_to_f32, grid_for(n), dim3(kBuildThreads), 0, s, pos64, type, n, ntypes, box[0], box[1],
-                           box[2], validate, pos32, err);
-    return hipGetLastError();
-}
-
 namespace {
 
 template <bool kCost>
@@ -809,15 +779,20 @@ Collapse collapse_model(float collapse_radius, int32_t leaf_size) {
 
 hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d_type, int32_t n, int32_t ntypes,
                         const float box[3], int32_t leaf_size, int32_t qbits, float collapse_radius, int32_t validate,
-                        hipStream_t s, const double *pos64, double *sorted64) {
+                        hipStream_t s, const double *pos64, double *sorted64, const double *box64) {
     const Collapse col = collapse_model(collapse_radius, leaf_size);
     const bool by_cost = col.kVball > 0.0f;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, w.type_count, w.err);
     const double sx = 1023.0 / (double)box[0];
     const double sy = 1023.0 / (double)box[1];
     const double sz = 1023.0 / (double)box[2];
-    hipLaunchKernelGGL(k_morton, grid_for((int64_t)n + 1), dim3(kBuildThreads), 0, s, d_pos, d_type, n, ntypes,
-                       box[0], box[1], box[2], sx, sy, sz, validate, w.keys, w.kept, w.err);
+    if (pos64 != nullptr)
+        hipLaunchKernelGGL(k_morton<double>, grid_for((int64_t)n + 1), dim3(kBuildThreads), 0, s, pos64, d_type, n,
+                           ntypes, box64[0], box64[1], box64[2], sx, sy, sz, validate, w.keys, w.kept, w.err);
+    else
+        hipLaunchKernelGGL(k_morton<float>, grid_for((int64_t)n + 1), dim3(kBuildThreads), 0, s, d_pos, d_type, n,
+                           ntypes, (double)box[0], (double)box[1], (double)box[2], sx, sy, sz, validate, w.keys,
+                           w.kept, w.err);
     hipError_t e = launch_radix_sort(w.keys, w.vals, w.keys2, w.vals2, w.hist, w.digit_total, n, w.tiles, s);
     if (e != hipSuccess) return e;
     if (ntypes > 1) hipLaunchKernelGGL(k_type_count, dim3(1), dim3(64), 0, s, w.keys, n, w.type_count);

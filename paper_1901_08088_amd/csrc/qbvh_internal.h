@@ -165,21 +165,20 @@ void fill_trav_box(TravArgs &a, const double box[3]);
 // Launchers (all asynchronous on `s`; return the launch status).
 // collapse_radius > 0: subtrees of at most leaf_size particles become runs by
 // the cost model (build_common.h); 0: every subtree of at most leaf_size.
-// The build from positions d_pos [n][3] (fp32).  fp64 data: d_pos holds the
-// data rounded to fp32 (the Morton codes' input) and pos64 the data itself,
-// from which the tree build gathers the particles (rounded to fp32, as in
-// d_pos) and writes sorted64 [n][4] in Z order.
+// The build from positions d_pos [n][3] (fp32) in box `box`.  fp64 data:
+// d_pos is null and pos64 [n][3] holds the data in the fp64 box box64 (box
+// is box64 rounded to fp32): the tree is built on the data rounded to
+// nearest fp32, validation is done in fp64, and sorted64 [n][4] receives the
+// fp64 positions in Z order.
 hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d_type, int32_t n,
                         int32_t ntypes, const float box[3], int32_t leaf_size, int32_t qbits,
                         float collapse_radius, int32_t validate, hipStream_t s, const double *pos64 = nullptr,
-                        double *sorted64 = nullptr);
+                        double *sorted64 = nullptr, const double *box64 = nullptr);
 hipError_t launch_traverse(const TravArgs &a, int32_t block, bool vec4, bool paper, const uint4 *qpoint,
                            hipStream_t s);
 // fp64 particle data: the positions rounded to fp32 for the build (with the
 // fp64 range and type checks when validate is set), and after the build the
 // fp64 positions in sorted order.
-hipError_t launch_to_f32(const double *pos64, const int32_t *type, int32_t n, int32_t ntypes, const double box[3],
-                         int32_t validate, float *pos32, int32_t *err, hipStream_t s);
 // Paper-mode cell boxes; lmax is the largest periodic box edge (the extent floor is lmax 2^-24).
 hipError_t launch_qpoint(const Workspace &w, int32_t n, int32_t ntypes, int32_t qbits, double lmax, hipStream_t s);
 hipError_t launch_traverse_batch(const BatchLaunch &b, hipStream_t s);
