@@ -111,6 +111,20 @@ def test_build_steps_duplicate_codes():
                           skin=0.1), leaf_size=2)
 
 
+@pytest.mark.parametrize("clusters,leaf_size,radius", [(33, 4, 0.0), (70, 16, 0.0), (70, 16, 1.5)])
+def test_build_steps_long_duplicate_runs(clusters, leaf_size, radius):
+    # runs of 1000 coincident or near-coincident points (equal Morton codes,
+    # ties by position) that cross first-level chunk borders and finish in
+    # the upper levels (70 clusters: two levels), with and without the cost model
+    rng = np.random.default_rng(9 + clusters)
+    n = clusters * 1000
+    base = rng.uniform(0, 30.0, size=(clusters, 3))
+    pos = np.repeat(base, 1000, axis=0) + rng.choice([0.0, 1e-3], size=(n, 3))
+    pos = W.wrap_f32(pos, np.full(3, 30.0, np.float32))
+    _step_parity(W.Config(pos=pos, box=np.full(3, 30.0, np.float32), rcut=np.array([[1.0]], np.float32),
+                          skin=0.1), leaf_size=leaf_size, collapse_radius=radius)
+
+
 def test_build_steps_three_types_one_empty():
     pos, box = W.uniform(6000, [14.0, 14.0, 14.0], seed=21)
     types = np.where(np.arange(6000) % 5 == 0, 3, 0).astype(np.int32)
