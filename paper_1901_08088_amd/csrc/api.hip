@@ -2,6 +2,7 @@
 // launch sequencing.  All device work is in build.hip, sort.hip and
 // traverse.hip; nothing here computes on the host beyond the per-call
 // constants (list radii, box scale factors).
+#include <algorithm>
 #include <math.h>
 #include <string.h>
 
@@ -372,8 +373,15 @@ int qbvh_export(const qbvh_t *tree, int32_t what, void *d_dst, size_t dst_bytes,
     case QBVH_EXPORT_RANGE_L: src = w.rl; bytes = n * 4; break;
     case QBVH_EXPORT_PARENT: src = w.parent; bytes = n * 4; break;
     case QBVH_EXPORT_LEAF_PARENT: src = w.leaf_parent; bytes = n * 4; break;
-    case QBVH_EXPORT_BOX_LO: src = w.box_lo; bytes = n * 16; break;
-    case QBVH_EXPORT_BOX_HI: src = w.box_hi; bytes = n * 16; break;
+    case QBVH_EXPORT_BOX_LO:
+    case QBVH_EXPORT_BOX_HI: {
+        // the bounds are stored interleaved (lower, upper per node): a strided copy
+        const size_t rows = std::min(n, dst_bytes / 16);
+        if (rows == 0 || !w.box) return QBVH_OK;
+        hipError_t e = hipMemcpy2DAsync(d_dst, 16, w.box + (what == QBVH_EXPORT_BOX_HI ? 1 : 0), 32, 16, rows,
+                                        hipMemcpyDeviceToDevice, (hipStream_t)stream);
+        return e == hipSuccess ? QBVH_OK : hip_fail(e);
+    }
     case QBVH_EXPORT_RECORDS: src = w.records; bytes = n * 32; break;
     case QBVH_EXPORT_ROPES: src = w.ropes; bytes = n * 4; break;
     default: return QBVH_EINVAL;

@@ -78,8 +78,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_type_count(int32_t nsys, co
 // Tree description of every (system, type).
 __global__ __launch_bounds__(64) void k_b_meta(int32_t nsys, const SysBuild *__restrict__ sysb,
                                                const uint32_t *__restrict__ type_count,
-                                               const float4 *__restrict__ sorted, const float4 *__restrict__ box_lo,
-                                               const float4 *__restrict__ box_hi, const uint32_t *__restrict__ P,
+                                               const float4 *__restrict__ sorted, const float4 *__restrict__ box,
+                                               const uint32_t *__restrict__ P,
                                                int32_t qbits, int32_t leaf_size, TreeMeta *__restrict__ meta) {
     const int32_t idx = blockIdx.x * 64 + threadIdx.x;
     const int32_t sys = idx / QBVH_MAX_TYPES, t = idx % QBVH_MAX_TYPES;
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(64) void k_b_meta(int32_t nsys, const SysBuild *__r
         lo[1] = hi[1] = p.y;
         lo[2] = hi[2] = p.z;
     } else if (c >= 2) {
-        const float4 a = box_lo[s], b = box_hi[s];
+        const float4 a = box[2 * (int64_t)s], b = box[2 * (int64_t)s + 1];
         lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
         hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
     }
@@ -112,8 +112,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_emit(const int32_t *__restr
                                                           const int32_t *__restrict__ left,
                                                           const int32_t *__restrict__ rf, const int32_t *__restrict__ rl,
                                                           const int32_t *__restrict__ parent,
-                                                          const float4 *__restrict__ box_lo,
-                                                          const float4 *__restrict__ box_hi,
+                                                          const float4 *__restrict__ box,
                                                           const uint32_t *__restrict__ P,
                                                           const TreeMeta *__restrict__ meta, int32_t leaf_size,
                                                           int32_t qbits, uint4 *__restrict__ records,
@@ -146,7 +145,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_b_emit(const int32_t *__restr
     if (threadIdx.x >= s_count) return;
     const int32_t k = s_ids[threadIdx.x];
     const TreeMeta &m = meta[it.sys * QBVH_MAX_TYPES + (keys[k] >> 30)];
-    emit_record(k, rf[k], rl[k], m, sorted, left, parent, box_lo, box_hi, P, leaf_size, nullptr, qbits, records,
+    emit_record(k, rf[k], rl[k], m, sorted, left, parent, box, P, leaf_size, nullptr, qbits, records,
                 ropes);
 }
 
@@ -173,11 +172,11 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t s) {
     e = launch_exclusive_scan(w.kept, b.total + 1, b.scan_part, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_b_meta, dim3((unsigned)((ninit + 63) / 64)), dim3(64), 0, s, b.nsys, b.sysb, b.type_count,
-                       w.sorted, w.box_lo, w.box_hi, w.kept, b.qbits, b.leaf_size, b.meta);
+                       w.sorted, w.box, w.kept, b.qbits, b.leaf_size, b.meta);
     if (b.total > 0)
         hipLaunchKernelGGL(k_b_emit, dim3((unsigned)b.blocks), dim3(kBuildThreads), 0, s, b.blk_first, b.nsys, b.sysb,
-                           w.keys, b.type_count, w.sorted, w.left, w.rf, w.rl, w.parent, w.box_lo,
-                           w.box_hi, w.kept, b.meta, b.leaf_size, b.qbits, w.records, w.ropes);
+                           w.keys, b.type_count, w.sorted, w.left, w.rf, w.rl, w.parent, w.box,
+                           w.kept, b.meta, b.leaf_size, b.qbits, w.records, w.ropes);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_traverse_batch(b, s);

@@ -149,7 +149,7 @@ __device__ __forceinline__ int32_t split_delta(const TreeSource &src, int32_t k,
 struct TreeOut {
     float4 *sorted;
     int32_t *left, *right, *rf, *rl, *parent, *leaf_parent;
-    float4 *box_lo, *box_hi;
+    float4 *box;      // [n][2]: lower and upper bound of each node
     uint32_t *kept;   // kept[l] counts the nodes [l, r] longer than kept_leaf
     float *cost;      // cost model only
     int32_t *delta;   // [n]: delta[k] for k < n - 1, delta[n - 1] = -1
@@ -165,8 +165,8 @@ __device__ __forceinline__ void write_node(const TreeOut &o, int32_t K, int32_t 
     o.rl[K] = r;
     o.left[K] = cl;
     o.right[K] = cr;
-    o.box_lo[K] = make_float4(lo[0], lo[1], lo[2], 0.0f);
-    o.box_hi[K] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+    o.box[2 * (int64_t)K] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+    o.box[2 * (int64_t)K + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
     if (kCost) o.cost[K] = cst;
     if (cl < 0) o.leaf_parent[~cl] = K; else o.parent[cl] = K;
     if (cr < 0) o.leaf_parent[~cr] = K; else o.parent[cr] = K;
@@ -362,8 +362,8 @@ __global__ __launch_bounds__(kFitThreads) void k_tree_local(const uint32_t *__re
             out.rl[K] = r;
             out.left[K] = g == l ? ~l : g;
             out.right[K] = g + 1 == r ? ~r : g + 1;
-            out.box_lo[K] = make_float4(s_box[0][t], s_box[1][t], s_box[2][t], 0.0f);
-            out.box_hi[K] = make_float4(s_box[3][t], s_box[4][t], s_box[5][t], 0.0f);
+            out.box[2 * (int64_t)K] = make_float4(s_box[0][t], s_box[1][t], s_box[2][t], 0.0f);
+            out.box[2 * (int64_t)K + 1] = make_float4(s_box[3][t], s_box[4][t], s_box[5][t], 0.0f);
             if (kCost) out.cost[K] = s_cost[t];
         }
         if (s_par[t] != kUnset) out.parent[K] = s_par[t];
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(kFitThreads) void k_tree_level(int32_t n, int64_t c
         } else {
             u.l = out.rf[c];
             u.r = out.rl[c];
-            const float4 a = out.box_lo[c], b = out.box_hi[c];
+            const float4 a = out.box[2 * (int64_t)c], b = out.box[2 * (int64_t)c + 1];
             u.lo[0] = a.x; u.lo[1] = a.y; u.lo[2] = a.z;
             u.hi[0] = b.x; u.hi[1] = b.y; u.hi[2] = b.z;
             u.cost = kCost ? out.cost[c] : 0.0f;
@@ -466,8 +466,8 @@ __global__ __launch_bounds__(kFitThreads) void k_tree_level(int32_t n, int64_t c
             out.slot[g] = kSlotDone;
             const int32_t sib = child_at(g, ex);
             // the sibling's box and cost and the new far weight, loaded together
-            const float4 *pa = sib < 0 ? out.sorted + ~sib : out.box_lo + sib;
-            const float4 *pb = sib < 0 ? out.sorted + ~sib : out.box_hi + sib;
+            const float4 *pa = sib < 0 ? out.sorted + ~sib : out.box + 2 * (int64_t)sib;
+            const float4 *pb = sib < 0 ? out.sorted + ~sib : out.box + 2 * (int64_t)sib + 1;
             const float4 slo = *pa, shi = *pb;
             const float scost = kCost ? (sib < 0 ? col.kVball : fabsf(out.cost[sib])) : 0.0f;
             const int32_t dnew = goes_left ? out.delta[ex] : (ex > 0 ? out.delta[ex - 1] : -1);
@@ -513,8 +513,8 @@ __global__ __launch_bounds__(kFitThreads) void k_tree_level(int32_t n, int64_t c
 
 // Root box, grid spacing and slot range of each type's tree.
 __global__ void k_meta(int32_t n, int32_t ntypes, const uint32_t *__restrict__ type_count,
-                       const float4 *__restrict__ sorted, const float4 *__restrict__ box_lo,
-                       const float4 *__restrict__ box_hi, const uint32_t *__restrict__ P, int32_t qbits,
+                       const float4 *__restrict__ sorted, const float4 *__restrict__ box,
+                       const uint32_t *__restrict__ P, int32_t qbits,
                        int32_t leaf_size, const float *__restrict__ cost, double ext_floor,
                        TreeMeta *__restrict__ meta) {
     const int t = threadIdx.x;
@@ -529,7 +529,7 @@ __global__ void k_meta(int32_t n, int32_t ntypes, const uint32_t *__restrict__ t
         lo[1] = hi[1] = p.y;
         lo[2] = hi[2] = p.z;
     } else if (c >= 2) {
-        const float4 a = box_lo[s], b = box_hi[s];
+        const float4 a = box[2 * (int64_t)s], b = box[2 * (int64_t)s + 1];
         lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
         hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
     }
@@ -585,8 +585,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_emit(int32_t n, int32_t ntype
                                                         const int32_t *__restrict__ left,
                                                         const int32_t *__restrict__ rf, const int32_t *__restrict__ rl,
                                                         const int32_t *__restrict__ parent,
-                                                        const float4 *__restrict__ box_lo,
-                                                        const float4 *__restrict__ box_hi,
+                                                        const float4 *__restrict__ box,
                                                         const uint32_t *__restrict__ P,
                                                         const TreeMeta *__restrict__ meta, int32_t leaf_size,
                                                         const uint32_t *__restrict__ kept_flag, int32_t qbits,
@@ -621,7 +620,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_emit(int32_t n, int32_t ntype
     for (uint32_t e = threadIdx.x; e < count; e += kBuildThreads) {
         const int32_t i = s_ids[e];
         const TreeMeta &m = meta[ntypes == 1 ? 0 : (keys[i] >> 30)];
-        emit_record(i, rf[i], rl[i], m, sorted, left, parent, box_lo, box_hi, P, leaf_size, kept_flag, qbits, records,
+        emit_record(i, rf[i], rl[i], m, sorted, left, parent, box, P, leaf_size, kept_flag, qbits, records,
                     ropes);
     }
 }
@@ -660,7 +659,7 @@ namespace {
 template <bool kCost>
 void launch_tree_t(const Workspace &w, int32_t n, const TreeSource &src, int32_t kept_leaf, const Collapse &col,
                    hipStream_t s) {
-    const TreeOut out{w.sorted, w.left, w.right, w.rf, w.rl, w.parent, w.leaf_parent, w.box_lo, w.box_hi, w.kept,
+    const TreeOut out{w.sorted, w.left, w.right, w.rf, w.rl, w.parent, w.leaf_parent, w.box, w.kept,
                       w.cost, reinterpret_cast<int32_t *>(w.visit), reinterpret_cast<int32_t *>(w.keys2), kept_leaf};
     int32_t nchunks = fit_chunks0(n);
     hipLaunchKernelGGL(k_tree_local<kCost>, dim3(nchunks), dim3(kFitThreads), 0, s, w.keys, w.vals, n, src, out,
@@ -708,7 +707,7 @@ size_t workspace_bytes(int32_t cap) {
     b += 6 * al(c * 4);                       // left right rf rl parent leaf_parent
     b += al(c * 4);                           // visit (split weights, then kept flags)
     b += al(c * 4);                           // cost (subtree collapse)
-    b += 2 * al(c * 16);                      // boxes
+    b += al(c * 32);                          // boxes (lower and upper bound per node)
     b += al((c + 1) * 4) + al(sb * 4);        // kept + scan partials
     b += al(c * 32) + al(c * 4);              // records + ropes
     b += al((c + kSortedPad) * 16);           // cell boxes (paper-mode lists)
@@ -747,8 +746,7 @@ void workspace_carve(Workspace &w, void *base, int32_t cap) {
     w.leaf_parent = (int32_t *)take(c * 4);
     w.visit = (uint32_t *)take(c * 4);
     w.cost = (float *)take(c * 4);
-    w.box_lo = (float4 *)take(c * 16);
-    w.box_hi = (float4 *)take(c * 16);
+    w.box = (float4 *)take(c * 32);
     w.kept = (uint32_t *)take((c + 1) * 4);
     w.scan_part = (uint32_t *)take(sb * 4);
     w.records = (uint4 *)take(c * 32);
@@ -809,12 +807,12 @@ hipError_t launch_build(const Workspace &w, const float *d_pos, const int32_t *d
     if (e != hipSuccess) return e;
     const double lmax = (double)fmaxf(box[0], fmaxf(box[1], box[2]));
     const double ext_floor = lmax * 0x1p-24;
-    hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, s, n, ntypes, w.type_count, w.sorted, w.box_lo, w.box_hi,
+    hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, s, n, ntypes, w.type_count, w.sorted, w.box,
                        w.kept, qbits, leaf_size, by_cost ? w.cost : nullptr, ext_floor, w.meta);
     if (n > 0)
         hipLaunchKernelGGL(k_emit, grid_for((n + kEmitItems - 1) / kEmitItems), dim3(kBuildThreads), 0, s, n, ntypes,
                            w.keys, w.type_count,
-                           w.sorted, w.left, w.rf, w.rl, w.parent, w.box_lo, w.box_hi, w.kept, w.meta,
+                           w.sorted, w.left, w.rf, w.rl, w.parent, w.box, w.kept, w.meta,
                            leaf_size, by_cost ? w.visit : nullptr, qbits, w.records, w.ropes);
     return hipGetLastError();
 }

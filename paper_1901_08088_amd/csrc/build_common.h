@@ -159,7 +159,7 @@ __device__ __forceinline__ TreeMeta tree_meta(const float lo[3], const float hi[
 __device__ __forceinline__ void emit_record(int32_t i, int32_t f, int32_t l, const TreeMeta &m,
                                             const float4 *__restrict__ sorted, const int32_t *__restrict__ left,
                                             const int32_t *__restrict__ parent,
-                                            const float4 *__restrict__ box_lo, const float4 *__restrict__ box_hi,
+                                            const float4 *__restrict__ box,
                                             const uint32_t *__restrict__ P, int32_t leaf_size,
                                             const uint32_t *__restrict__ kept_flag, int32_t qbits,
                                             uint4 *__restrict__ records, int32_t *__restrict__ ropes) {
@@ -172,8 +172,8 @@ __device__ __forceinline__ void emit_record(int32_t i, int32_t f, int32_t l, con
     for (int side = 0; side < 2; ++side) {
         const bool leaf = cf[side] == cl[side];
         const int32_t k = side == 0 ? g : g + 1;
-        lo[side] = *(leaf ? sorted + k : box_lo + k);
-        hi[side] = *(leaf ? sorted + k : box_hi + k);
+        lo[side] = *(leaf ? sorted + k : box + 2 * (int64_t)k);
+        hi[side] = *(leaf ? sorted + k : box + 2 * (int64_t)k + 1);
     }
     const uint32_t right_rec = P[g + 1];
     const int32_t rope = (int32_t)P[l + 1];

@@ -59,7 +59,7 @@ struct Workspace {
     int32_t *parent = nullptr, *leaf_parent = nullptr;
     uint32_t *visit = nullptr;      // split weights during the tree build; with the cost model, then kept flags
     float *cost = nullptr;          // subtree collapse: volume-weighted cost per internal node (negative: a run)
-    float4 *box_lo = nullptr, *box_hi = nullptr;
+    float4 *box = nullptr;          // [cap][2]: node K's lower bound at 2K, its upper bound at 2K + 1
     uint32_t *kept = nullptr;       // [cap + 1]: kept-node counts, scanned in place
     uint32_t *scan_part = nullptr;  // [scan blocks + 1]
     uint4 *records = nullptr;       // [cap][2]: two-wide quantized records
