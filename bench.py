@@ -166,12 +166,12 @@ def band_report(cfg, queries=None, threads: int = 0) -> dict:
 # factor the same counters read for a plain elementwise copy of known size (the
 # --copy-probe-mib kernel).  Valid only for the kernel sources it was taken on:
 # ``traffic`` is reported as null once their hash differs.
-TRAFFIC = {"sources": "d445cf3b6d26f71a", "workload": "lj8m",
+TRAFFIC = {"sources": "46520ba402bbbee4", "workload": "lj8m",
            "opts": {"leaf_size": 16, "qbits": 16, "block_size": 64},
-           "fetch_kib": 1527764.0, "write_kib": 6609965.0, "copy_factor": 1.0,
+           "fetch_kib": 1528910.0, "write_kib": 6610126.0, "copy_factor": 1.0,
            # FETCH_SIZE per byte read: 0.500 for vector loads (the copy probe), 1.000 for
            # scalar loads (profiles/fetch_size_calibration.md)
-           "fetch_factor": 0.500013, "fetch_factor_scalar": 1.000049,
+           "fetch_factor": 0.500012, "fetch_factor_scalar": 1.000049,
            "profile": "profiles/k_traverse_lj8m_counters.md",
            # SQ_INSTS_VALU x 4 / (1024 SIMDs x kernel cycles): the VALU issues one wave64
            # instruction per 4 cycles per SIMD, so this is the kernel's VALU issue roofline
